@@ -1,0 +1,177 @@
+/*
+ * biotlbm.h -- C ABI of the MI355X (gfx950) solver for the semi-implicit lattice
+ * Boltzmann scheme for Biot's consolidation model of Lunowa & Wohlmuth,
+ * "A lattice Boltzmann method for Biot's consolidation model of linear
+ * poroelasticity" (arXiv:2409.11382).
+ *
+ * Problem (Sec. 2.1, eqs. 1-4): find displacement eta and pressure p with
+ *   -div sigma + alpha grad p = f,  sigma = lambda div(eta) I + mu (grad eta + grad eta^T),
+ *   d/dt (c0 p + alpha div eta) + div u = s,  u = -kappa grad p,
+ * on a rectangle of nx x ny cells of width dx, time step dt, with periodic,
+ * Dirichlet or Neumann (no-flow / traction) boundary conditions (Sec. 3.6) and a
+ * symmetry (roller, impermeable mirror) condition.
+ *
+ * Method per time step (Algorithm 5): explicit force, N_E multigrid cycles
+ * (Algorithm 4) of the pseudo-time MRT elasticity LBM (Algorithm 2, Tables 2-3),
+ * then one SRT flow step (Algorithm 3) with the centred coupling source
+ * (eq. source:implicit, ratio r).
+ *
+ * Conventions
+ *   - Every function returns a bp_status; nothing throws across the ABI.  On an
+ *     error bp_last_error() returns a message for the calling thread.
+ *   - Host arrays are row-major [y][x] (x fastest), vector fields component
+ *     first; they are read during the call and not retained.
+ *   - Device memory: the caller allocates one workspace of bp_workspace_bytes()
+ *     bytes (256-byte aligned) and passes it to bp_create; the library never
+ *     allocates device memory.  The workspace must outlive the solver.
+ *   - All device work is enqueued on the HIP stream given to bp_create
+ *     (NULL = legacy default stream).  Calls on one solver are not thread-safe.
+ *   - Inputs are dimensional; the library converts to lattice units.
+ */
+#ifndef BIOTLBM_H
+#define BIOTLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BP_OK = 0,
+  BP_ERR_ARG = -1,        /* invalid argument or parameter */
+  BP_ERR_SHAPE = -2,      /* grid not compatible with the level hierarchy */
+  BP_ERR_DEVICE = -3,     /* a HIP call failed */
+  BP_ERR_DIVERGED = -4,   /* non-finite populations or residual norms */
+  BP_ERR_WORKSPACE = -5,  /* workspace missing, misaligned or too small */
+  BP_ERR_STATE = -6       /* solver unusable after an earlier error */
+} bp_status;
+
+/* population storage and collision precision; "shifted" stores populations as
+ * offsets from a per-cell displacement / pressure reference (re-based every
+ * step).  Divergence fields, the coupling source, residual norms and the
+ * coarsest multigrid level are FP64 in every mode. */
+typedef enum { BP_FP64 = 0, BP_FP32 = 1, BP_FP32_SHIFTED = 2, BP_FP64_SHIFTED = 3 } bp_precision;
+
+/* flow boundary types (Sec. 3.6): periodic, pressure Dirichlet (halfway
+ * anti-bounce-back, eq. BC:pressure), no flow (halfway bounce-back,
+ * eq. BC:noFlow), symmetry (mirror reflection; impermeable) */
+enum { BP_FLOW_PERIODIC = 0, BP_FLOW_DIRICHLET = 1, BP_FLOW_NOFLOW = 2, BP_FLOW_SYMMETRY = 3 };
+/* elastic boundary types (Sec. 3.6): periodic, displacement Dirichlet
+ * (eq. BC:elasticity), traction (eq. BC:traction), symmetry (roller: zero normal
+ * displacement and zero shear traction, mirror reflection) */
+enum { BP_EL_PERIODIC = 0, BP_EL_DIRICHLET = 1, BP_EL_TRACTION = 2, BP_EL_SYMMETRY = 3 };
+enum { BP_LEFT = 0, BP_RIGHT = 1, BP_BOTTOM = 2, BP_TOP = 3 };
+
+/* One side of the domain.  Left/right arrays have ny entries (indexed by row),
+ * bottom/top arrays nx entries (indexed by column); data are given at the face
+ * centre of each boundary cell.  Periodic must hold on both opposite sides for
+ * both fields. */
+typedef struct {
+  int32_t el;               /* BP_EL_*, uniform along the side */
+  int32_t flow_uniform;     /* BP_FLOW_* used when flow_type is NULL */
+  const int8_t *flow_type;  /* per boundary cell BP_FLOW_*, or NULL */
+  const double *el_value;   /* 2 per boundary cell: eta_D (Dirichlet) or traction
+                               t = sigma n (traction); NULL means zero */
+  const double *p_value;    /* 1 per boundary cell: p_D; NULL means zero */
+} bp_side;
+
+typedef struct {
+  int32_t nx, ny;           /* cells */
+  double dx, dt;            /* cell width, time step (> 0) */
+  double lambda, mu;        /* Lame coefficients: mu > 0, lambda + mu > 0 */
+  double c0;                /* specific storage (> 0; Sec. 2.2 excludes c0 = 0) */
+  double alpha;             /* Biot-Willis coefficient in [0, 1] */
+  const double *kappa;      /* per-cell permeability (N values) or NULL */
+  double kappa_uniform;     /* permeability when kappa is NULL (> 0) */
+  const double *body_f;     /* body force f, 2 x N, or NULL (zero) */
+  const double *source_s;   /* fluid source s, N, or NULL (zero) */
+  double r;                 /* explicit/implicit coupling ratio in [0, 1]; 0.5 = centred */
+  int32_t levels;           /* multigrid levels L (0 = as many halvings as keep >= 2 cells) */
+  int32_t K;                /* pre- and post-smoothing steps (>= 1) */
+  double gamma;             /* smoother under-relaxation in (0, 1) */
+  int32_t ne_fixed;         /* > 0: that many V-cycles per time step */
+  double ne_tol;            /* ne_fixed == 0: stop when ||g - S(g)|| <= ne_tol ||g|| */
+  int32_t ne_max;           /* ne_fixed == 0: at most this many V-cycles */
+  bp_side side[4];
+  int32_t prec;             /* bp_precision */
+} bp_problem;
+
+typedef struct bp_solver bp_solver;
+
+typedef struct {
+  int32_t step;             /* completed time steps */
+  int32_t last_ne;          /* V-cycles of the last step */
+  int64_t total_cycles;     /* V-cycles since creation */
+  double last_ratio;        /* last ||g - S(g)|| / ||g|| measured (adaptive mode; else -1) */
+  int32_t levels;           /* multigrid levels in use */
+  int32_t diverged;         /* non-finite norm seen */
+} bp_run_stats;
+
+/* Device bytes needed for problem p (host-only, pure). */
+bp_status bp_workspace_bytes(const bp_problem *p, size_t *device_bytes);
+
+/* Validate p, convert to lattice units (Sec. 2.2), build the level hierarchy
+ * (Sec. 3.5: each coarse cell covers 2x2 fine cells; homogeneous boundary data
+ * on coarse levels), upload parameters and boundary data into device_ws and set
+ * the initial conditions (eqs. ICs, ICs:moments).  hip_stream is a hipStream_t
+ * or NULL.  *out owns host metadata only. */
+bp_status bp_create(const bp_problem *p, void *device_ws, size_t ws_bytes, void *hip_stream,
+                    bp_solver **out);
+
+/* Advance nsteps coupled time steps (Algorithm 5).  Asynchronous on the
+ * solver's stream in fixed-N_E mode (one captured HIP graph per step); the
+ * adaptive mode synchronises once per V-cycle to read the residual ratio. */
+bp_status bp_step(bp_solver *s, int32_t nsteps);
+
+/* Replace body force and fluid source (host arrays, NULL = zero) for the next
+ * steps; reinit != 0 also resets the state to the initial conditions. */
+bp_status bp_set_loads(bp_solver *s, const double *body_f, const double *source_s, int32_t reinit);
+
+/* Synchronise and copy the fields of the last completed step n (time n dt):
+ * eta (2 x N), p (N), sigma (3 x N: 11, 12, 22) in dimensional units; any
+ * pointer may be NULL.  Returns BP_ERR_DIVERGED if the state is not finite. */
+bp_status bp_get_fields(bp_solver *s, double *eta, double *p, double *sigma, int32_t *step);
+
+/* Checkpoint access in FP64 component planes: f (9 x N, D2Q9 order of Table 1),
+ * g (8 x N, D2Q8 order 10,01,-10,0-1,11,-11,-1-1,1-1, full populations),
+ * D1 = D^{n-1}, D2 = D^{n-2} (lattice divergences, N each).  bp_set_state also
+ * sets the step counter. */
+bp_status bp_get_state(bp_solver *s, double *f, double *g, double *D1, double *D2, int32_t *step);
+bp_status bp_set_state(bp_solver *s, const double *f, const double *g, const double *D1,
+                       const double *D2, int32_t step);
+
+/* Single operations on host FP64 planes (lattice units), for inspection:
+ * out = S(g) = ELASTIC_STEP(g - r, Ft + F_*(g)) on level l (l = levels is the
+ * finest, Algorithm 4 line with g**), one ELASTIC_MULTIGRID cycle on level l
+ * (g in/out), and the explicit force of the current state (2 x N). */
+bp_status bp_apply_elastic(bp_solver *s, int32_t level, const double *g, const double *r,
+                           const double *Ft, double *out);
+bp_status bp_mg_cycle(bp_solver *s, int32_t level, double *g, const double *r, const double *Ft);
+bp_status bp_explicit_force(bp_solver *s, double *Ft);
+bp_status bp_level_shape(const bp_solver *s, int32_t level, int32_t *nx, int32_t *ny);
+
+bp_status bp_stats(const bp_solver *s, bp_run_stats *st);
+
+/* Average device time (microseconds, HIP events on the solver's stream) of
+ * `iters` back-to-back launches of one kernel on the current state:
+ * which = 0 finest-level smoothing sweep, 1 finest-level residual/restriction,
+ * 2 flow step, 3 explicit force.  *bytes receives the algorithmic HBM bytes of
+ * one launch (each value the kernel must read or write, once).  The state is
+ * left unchanged. */
+bp_status bp_time_kernel(bp_solver *s, int32_t which, int32_t iters, double *avg_us, double *bytes);
+
+/* Plain device copy of `bytes` (multiple of 16) on a stream; used to calibrate
+ * hardware byte counters. */
+bp_status bp_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+bp_status bp_destroy(bp_solver *s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *bp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIOTLBM_H */

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Bars: single operations 1e-13 relative, whole FP64 steps 1e-10 relative
+(element-wise over all cells), FP32 paths 1e-5 relative L2 for eta and p.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import oracle_threads
+from gpu_helpers import mixed_walls, problems_small, rel
+from oracle.oracle import Oracle
+from paper_2409_11382_amd import problem as P
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 1e-13
+STEP_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_11382_amd import lbm as L
+
+    L.load_library()
+    return L
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rand_state(p, seed):
+    f, g, d1, d2 = P.random_state(p, seed, scale=1e-2)
+    return f, g, d1, d2
+
+
+@pytest.mark.parametrize("name", list(problems_small().keys()))
+def test_apply_elastic_every_level(lbm, name):
+    p = problems_small()[name]
+    _say("apply_elastic", name, p.nx, p.ny)
+    s = lbm.Solver(p, "fp64")
+    o = Oracle(p, threads=oracle_threads())
+    L = o.levels
+    rng = np.random.default_rng(7)
+    for level in range(L, 0, -1):
+        nx, ny = o.level_shape(level)
+        assert s.level_shape(level) == (nx, ny)
+        g = rng.standard_normal((8, ny, nx))
+        if level == L:
+            Ft = rng.standard_normal((2, ny, nx)) * 0.1
+            a = s.apply_elastic(level, g, None, Ft)
+            b = o.apply_elastic(level, g, None, Ft)
+        else:
+            r = rng.standard_normal((8, ny, nx)) * 0.1
+            a = s.apply_elastic(level, g, r, None)
+            b = o.apply_elastic(level, g, r, None)
+        err = np.abs(a - b).max() / np.abs(b).max()
+        _say("  level", level, (nx, ny), "max rel", err)
+        assert err < OP_TOL
+
+
+@pytest.mark.parametrize("name", list(problems_small().keys()))
+def test_vcycle_and_force(lbm, name):
+    p = problems_small()[name]
+    _say("vcycle", name)
+    s = lbm.Solver(p, "fp64")
+    o = Oracle(p, threads=oracle_threads())
+    f, g, d1, d2 = _rand_state(p, 11)
+    o.set_state(f, g, d1, d2, step=5)
+    s.set_state(f, g, d1, d2, step=5)
+    Fa, Fb = s.explicit_force(), o.explicit_force()
+    _say("  force rel", rel(Fa, Fb))
+    assert np.abs(Fa - Fb).max() <= OP_TOL * np.abs(Fb).max()
+    L = o.levels
+    ga = s.mg_cycle(L, g, None, Fb)
+    gb = o.mg_cycle(L, g, None, Fb)
+    err = np.abs(ga - gb).max() / np.abs(gb).max()
+    _say("  vcycle max rel", err)
+    assert err < 1e-12
+
+
+def _compare_steps(lbm, p, nsteps, prec="fp64", loads=None, tol=STEP_TOL, check_every=None):
+    s = lbm.Solver(p, prec)
+    o = Oracle(p, threads=oracle_threads())
+    if loads is not None:
+        f0, s0 = loads(0.0)
+        o.set_loads(f0, s0, reinit=True)
+        s.set_loads(f0, s0, reinit=True)
+    worst = 0.0
+    for k in range(nsteps):
+        if loads is not None and k > 0:
+            fk, sk = loads(k * p.dt)
+            o.set_loads(fk, sk)
+            s.set_loads(fk, sk)
+        o.step(1)
+        s.step(1)
+        if check_every and (k + 1) % check_every == 0 or k == nsteps - 1:
+            A, B = s.fields(), o.fields()
+            e = max(rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+            worst = max(worst, e)
+            assert e < tol, (k, rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+    return worst, s, o
+
+
+@pytest.mark.parametrize("name", list(problems_small().keys()))
+def test_fp64_steps_match_oracle(lbm, name):
+    p = problems_small()[name]
+    _say("fp64 steps", name)
+    worst, s, o = _compare_steps(lbm, p, 6, check_every=2)
+    A, B = s.fields(), o.fields()
+    # element-wise bar on every cell as well
+    scale = np.abs(B["eta"]).max()
+    assert np.abs(A["eta"] - B["eta"]).max() <= STEP_TOL * scale
+    assert np.abs(A["p"] - B["p"]).max() <= STEP_TOL * np.abs(B["p"]).max()
+    _say("  worst rel", worst)
+
+
+def test_manufactured_time_dependent_loads(lbm):
+    M = P.Manufactured(32, alpha=1.0, r=0.5, K=2, ne_fixed=3)
+    worst, _, _ = _compare_steps(lbm, M.problem, 12, loads=M.loads, check_every=3)
+    _say("manufactured worst rel", worst)
+
+
+def test_adaptive_cycles_follow_oracle(lbm):
+    """Configuration 1 (Terzaghi 8x128, tolerance 1e-8, at most 50 cycles): the
+    GPU's V-cycle counts are replayed by the oracle; the oracle's own adaptive
+    decisions agree except at near-ties of the residual ratio."""
+    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50)
+    nsteps = 12
+    s = lbm.Solver(p, "fp64")
+    ne = []
+    for _ in range(nsteps):
+        s.step(1)
+        ne.append(s.stats()["last_ne"])
+    _say("gpu N_E", ne)
+    o = Oracle(p.replace(ne_fixed=0), threads=oracle_threads(), history=nsteps)
+    o.set_ne_schedule(np.array(ne, dtype=np.int32))
+    o.step(nsteps)
+    A, B = s.fields(), o.fields()
+    assert rel(A["eta"], B["eta"]) < STEP_TOL and rel(A["p"], B["p"]) < STEP_TOL
+    # a tighter tolerance that the cycles do reach
+    p2 = P.terzaghi(nx=8, ny=32, ne_fixed=0, ne_tol=1e-6, ne_max=40)
+    s2 = lbm.Solver(p2, "fp64")
+    ne2 = []
+    for _ in range(8):
+        s2.step(1)
+        ne2.append(s2.stats()["last_ne"])
+    o2 = Oracle(p2, threads=1, history=8)
+    o2.step(8)
+    ne_o, ratio_o = o2.get_history()
+    _say("gpu", ne2, "oracle", list(ne_o))
+    assert ne2 == list(ne_o)
+    assert rel(s2.fields()["eta"], o2.fields()["eta"]) < STEP_TOL
+
+
+def test_zero_load_is_exactly_zero_on_gpu(lbm):
+    for prec in ("fp64", "fp32", "fp32_shifted"):
+        p = P.loaded_strip(n=64, load=0.0, ne_fixed=2)
+        s = lbm.Solver(p, prec)
+        s.step(4)
+        F = s.fields()
+        assert not np.any(F["eta"]) and not np.any(F["p"]) and not np.any(F["sigma"]), prec
+
+
+def test_shifted_fp64_equals_plain_fp64(lbm):
+    p = mixed_walls(124, 68, seed=5)
+    a = lbm.Solver(p, "fp64")
+    b = lbm.Solver(p, "fp64_shifted")
+    a.step(8)
+    b.step(8)
+    A, B = a.fields(), b.fields()
+    _say("shift rel", rel(B["eta"], A["eta"]), rel(B["p"], A["p"]))
+    assert rel(B["eta"], A["eta"]) < 1e-13 and rel(B["p"], A["p"]) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32_shifted", 1e-5), ("fp32", 1e-2)])
+def test_fp32_paths_against_fp64_oracle(lbm, prec, tol):
+    """FP32 with shifted storage must stay within 1e-5 of the FP64 oracle.  Plain
+    FP32 is the ablation: the stress moments cancel against the displacement
+    equilibrium and lose about log10(N) digits; it is only bounded here."""
+    p = P.loaded_strip(n=128, alpha=1.0, ne_fixed=3)
+    nsteps = 40
+    s = lbm.Solver(p, prec)
+    o = Oracle(p, threads=oracle_threads())
+    s.step(nsteps)
+    o.step(nsteps)
+    A, B = s.fields(), o.fields()
+    e_eta, e_p = rel(A["eta"], B["eta"]), rel(A["p"], B["p"])
+    _say(prec, "rel eta", e_eta, "rel p", e_p)
+    assert e_eta < tol and e_p < tol
+
+
+def test_determinism_and_mirror_symmetry(lbm):
+    p = P.loaded_strip(n=256, alpha=1.0, ne_fixed=3)
+    a = lbm.Solver(p, "fp64")
+    b = lbm.Solver(p, "fp64")
+    a.step(5)
+    b.step(5)
+    A, B = a.fields(), b.fields()
+    assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+    assert np.abs(A["eta"][0] + A["eta"][0][:, ::-1]).max() < 1e-12 * np.abs(A["eta"]).max()
+    assert np.abs(A["p"] - A["p"][:, ::-1]).max() < 1e-12 * np.abs(A["p"]).max()
+
+
+def test_checkpoint_resume_is_bitwise(lbm):
+    p = P.loaded_strip(n=64, alpha=0.8, ne_fixed=3)
+    a = lbm.Solver(p, "fp64")
+    a.step(6)
+    st = a.get_state()
+    a.step(4)
+    b = lbm.Solver(p, "fp64")
+    b.set_state(st["f"], st["g"], st["D1"], st["D2"], step=st["step"])
+    b.step(4)
+    A, B = a.fields(), b.fields()
+    assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+
+
+def test_full_size_loaded_strip_512(lbm):
+    """The benchmarked workload (loaded strip 512 x 512, alpha = 1, MG(3,4)) at
+    its real size for a few steps, FP64 against the oracle, plus the FP32
+    shifted path's error."""
+    p = P.loaded_strip(n=512, alpha=1.0, ne_fixed=3)
+    nsteps = 3
+    o = Oracle(p, threads=oracle_threads())
+    o.step(nsteps)
+    B = o.fields()
+    for prec, tol in (("fp64", STEP_TOL), ("fp32_shifted", 1e-5)):
+        s = lbm.Solver(p, prec)
+        s.step(nsteps)
+        A = s.fields()
+        e = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+        _say("512", prec, e)
+        assert e[0] < tol and e[1] < tol
+
+
+def test_invalid_problems_rejected(lbm):
+    base = P.loaded_strip(n=16)
+    for bad in (dict(c0=0.0), dict(alpha=1.5), dict(gamma=1.0), dict(levels=6)):
+        with pytest.raises(lbm.BiotError):
+            lbm.Solver(base.replace(**bad))
