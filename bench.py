@@ -2,7 +2,7 @@
 
 Workload: the 2D loaded-strip consolidation problem on 512 x 512 cells (unit load
 on the central quarter of the top, drained elsewhere on the top, impermeable
-rollers on the other sides; E = 1, nu = 0.3, kappa = 1, c0 = 0.1, alpha = 1;
+rollers on the other sides; E = 1, nu = 0.3, kappa = 1, c0 = 1, alpha = 1;
 multigrid with 9 levels, K = 4, gamma = 3/4, 3 V-cycles per step, centred
 coupling r = 1/2).  A step is one full coupled time step (explicit force, three
 V-cycles, flow update) over the whole grid; inputs are resident in HBM.
@@ -109,10 +109,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"loaded_strip_{args.n}x{args.n}", "alpha": 1.0, "nu": 0.3, "E": 1.0,
-                   "kappa": 1.0, "c0": 0.1, "levels": prob.num_levels(), "K": 4, "gamma": 0.75,
-                   "ne_fixed": 3, "r": 0.5, "precision": "fp32_shifted (fp64 D, coupling, norms, coarsest)"},
-        "roofline": {"bound": "hbm", "kernel": "finest-level smoothing sweep (k_sweep<float,float,smooth,shift>)",
+        "config": {"workload": f"loaded_strip_{args.n}x{args.n}", "alpha": prob.alpha, "nu": 0.3, "E": 1.0,
+                   "kappa": float(prob.kappa), "c0": prob.c0, "levels": prob.num_levels(), "K": prob.K,
+                   "gamma": prob.gamma, "ne_fixed": prob.ne_fixed, "r": prob.r,
+                   "precision": "fp32_shifted (fp64 D, coupling, norms, coarsest)"},
+        "roofline": {"bound": "hbm", "kernel": "finest-level smoothing sweep (k_tsweep<float,float,smooth,shift>)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_us": round(us, 3), "bytes_per_launch": nbytes},

@@ -168,6 +168,21 @@ bp_status bp_device_copy(void *dst, const void *src, size_t bytes, void *hip_str
 
 bp_status bp_destroy(bp_solver *s);
 
+/* ---- batches: many independent problems advanced together.  Every launch of
+ * a time step covers the same multigrid depth of all problems (levels aligned
+ * from the finest), so n problems cost about the launches of one.  Problems
+ * must share the precision, K and the fixed number of V-cycles; grids,
+ * parameters and boundary data may differ.  Results are bitwise identical to
+ * solving each problem alone. */
+typedef struct bp_batch bp_batch;
+bp_status bp_batch_workspace_bytes(const bp_problem *probs, int32_t n, size_t *device_bytes);
+bp_status bp_batch_create(const bp_problem *probs, int32_t n, void *device_ws, size_t ws_bytes,
+                          void *hip_stream, bp_batch **out);
+bp_status bp_batch_step(bp_batch *b, int32_t nsteps);
+bp_status bp_batch_get_fields(bp_batch *b, int32_t i, double *eta, double *p, double *sigma,
+                              int32_t *step);
+bp_status bp_batch_destroy(bp_batch *b);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *bp_last_error(void);
 

@@ -1,17 +1,21 @@
 // Host side of the MI355X Biot LBM library: validation, conversion to lattice
-// units, workspace layout, boundary terms, the multigrid schedule (Algorithm 4),
-// the coupled step (Algorithm 5), HIP-graph capture and the C ABI of biotlbm.h.
+// units, per-problem workspace layout, boundary-link terms, the batched engine
+// (device descriptors, tile lists, the multigrid schedule of Algorithm 4 inside
+// the coupled step of Algorithm 5, HIP-graph capture) and the C ABI of
+// biotlbm.h.  A single solver is an engine of one problem.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
 #include "../../include/biotlbm.h"
-#include "lbm_kernels.h"
+#include "lbm_engine.h"
 
 using namespace biot;
 
@@ -24,16 +28,16 @@ bp_status fail(bp_status st, const std::string& msg) {
   return st;
 }
 
-#define HIPCHK(call)                                                                       \
-  do {                                                                                     \
-    hipError_t e_ = (call);                                                                \
+#define HIPCHK(call)                                                                                      \
+  do {                                                                                                    \
+    hipError_t e_ = (call);                                                                               \
     if (e_ != hipSuccess) return fail(BP_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-#define BPCHK(call)                    \
-  do {                                 \
-    bp_status st_ = (call);            \
-    if (st_ != BP_OK) return st_;      \
+#define BPCHK(call)               \
+  do {                            \
+    bp_status st_ = (call);       \
+    if (st_ != BP_OK) return st_; \
   } while (0)
 
 constexpr size_t kAlign = 256;
@@ -49,7 +53,6 @@ const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0
 
 int side_len(int side, int nx, int ny) { return (side == kLeft || side == kRight) ? ny : nx; }
 
-// does population (cx, cy) enter the domain through `side`?
 bool enters_through(int side, int cx, int cy) {
   switch (side) {
     case kLeft: return cx > 0;
@@ -69,41 +72,7 @@ int default_levels(int nx, int ny) {
   return L;
 }
 
-struct LevelBuf {
-  int nx = 0, ny = 0, pitch = 0;
-  int64_t plane = 0;
-  bool dbl = false;     // FP64 storage
-  size_t oA = 0, oB = 0, oR = 0;  // offsets (oR = 0 -> none)
-  void* gA = nullptr;
-  void* gB = nullptr;
-  void* r = nullptr;
-  int H = 16;
-};
-
-// Layout of all device buffers carved out of the caller's workspace.
-struct Layout {
-  int L = 1, nx = 0, ny = 0, pitch = 0;
-  int64_t plane = 0;
-  bool fdbl = true, shift = false;
-  std::vector<LevelBuf> lv;  // 1..L
-  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
-  size_t off_eta, off_sig, off_part, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
-  int max_waves = 0;
-  size_t total = 0;
-};
-
 int pitch_for(int nx) { return (nx + 31) / 32 * 32; }
-
-int choose_H(int nx, int ny) {
-  if (const char* e = std::getenv("BIOT_SWEEP_H")) {
-    int h = std::atoi(e);
-    if (h >= 2 && h % 2 == 0) return h;
-  }
-  const int hs[] = {32, 16, 8, 4};
-  for (int h : hs)
-    if (sweep_waves(nx, ny, h) >= 2048) return h;
-  return 4;
-}
 
 bp_status validate(const bp_problem* p) {
   if (!p) return fail(BP_ERR_ARG, "null problem");
@@ -134,14 +103,34 @@ bp_status validate(const bp_problem* p) {
       (p->side[kBottom].el == BP_EL_PERIODIC) != (p->side[kTop].el == BP_EL_PERIODIC))
     return fail(BP_ERR_ARG, "periodic sides must come in opposite pairs");
   const int L = p->levels > 0 ? p->levels : default_levels(p->nx, p->ny);
-  if (L > 30 || p->nx % (1 << (L - 1)) || p->ny % (1 << (L - 1)))
-    return fail(BP_ERR_SHAPE, "nx and ny must be divisible by 2^(levels-1)");
+  if (L > kMaxLevels || p->nx % (1 << (L - 1)) || p->ny % (1 << (L - 1)))
+    return fail(BP_ERR_SHAPE, "nx and ny must be divisible by 2^(levels-1) (at most 16 levels)");
   const int cx = p->nx >> (L - 1), cy = p->ny >> (L - 1);
   const bool perx = p->side[kLeft].el == BP_EL_PERIODIC, pery = p->side[kBottom].el == BP_EL_PERIODIC;
   if ((!perx && cx < 2) || (!pery && cy < 2))
     return fail(BP_ERR_SHAPE, "a non-periodic direction needs >= 2 cells on the coarsest level");
   return BP_OK;
 }
+
+// ---------------------------------------------------------------- layout
+struct LevelLay {
+  int nx = 0, ny = 0, pitch = 0;
+  int64_t plane = 0;
+  bool dbl = false;
+  size_t oA = 0, oB = 0, oR = 0;  // oR == SIZE_MAX: none
+};
+
+// offsets of all device buffers of one problem, relative to its base
+struct Layout {
+  int L = 1, nx = 0, ny = 0, pitch = 0;
+  int64_t plane = 0;
+  bool fdbl = true, shift = false;
+  std::vector<LevelLay> lv;  // 1..L
+  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
+  size_t off_eta, off_sig, off_part, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
+  int ntiles_fine = 0;
+  size_t total = 0;
+};
 
 void make_layout(const bp_problem* p, Layout& lo) {
   lo.L = p->levels > 0 ? p->levels : default_levels(p->nx, p->ny);
@@ -158,10 +147,9 @@ void make_layout(const bp_problem* p, Layout& lo) {
     off += align_up(bytes);
     return o;
   };
-  lo.lv.assign(lo.L + 1, LevelBuf());
-  lo.max_waves = 1;
+  lo.lv.assign(lo.L + 1, LevelLay());
   for (int l = lo.L; l >= 1; --l) {
-    LevelBuf& v = lo.lv[l];
+    LevelLay& v = lo.lv[l];
     v.nx = p->nx >> (lo.L - l);
     v.ny = p->ny >> (lo.L - l);
     v.pitch = pitch_for(v.nx);
@@ -171,9 +159,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
     const size_t es = v.dbl ? 8 : 4;
     v.oA = take(8 * v.plane * es);
     v.oB = take(8 * v.plane * es);
-    v.oR = (l < lo.L) ? take(8 * v.plane * es) : 0;
-    v.H = choose_H(v.nx, v.ny);
-    lo.max_waves = std::max(lo.max_waves, sweep_waves(v.nx, v.ny, v.H));
+    v.oR = (l < lo.L) ? take(8 * v.plane * es) : SIZE_MAX;
   }
   lo.off_f[0] = take(9 * lo.plane * fs);
   lo.off_f[1] = take(9 * lo.plane * fs);
@@ -183,12 +169,13 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.off_src = take(lo.plane * 8);
   lo.off_omf = take(lo.plane * 8);
   lo.off_Ft = take(2 * lo.plane * fs);
-  lo.off_eref = lo.shift ? take(2 * lo.plane * fs) : 0;
-  lo.off_pref = lo.shift ? take(lo.plane * fs) : 0;
+  lo.off_eref = lo.shift ? take(2 * lo.plane * fs) : SIZE_MAX;
+  lo.off_pref = lo.shift ? take(lo.plane * fs) : SIZE_MAX;
   const size_t N = (size_t)p->nx * p->ny;
   lo.off_eta = take(2 * N * 8);
   lo.off_sig = take(3 * N * 8);
-  lo.off_part = take((size_t)lo.max_waves * 2 * 8);
+  lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
+  lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
   lo.off_scal = take(64);
   for (int s = 0; s < 4; ++s) {
     const int n = side_len(s, p->nx, p->ny);
@@ -199,363 +186,31 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.total = off;
 }
 
-}  // namespace
-
-// ===================================================================== solver
-struct bp_solver {
-  Layout lo;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  // problem scalars
-  int nx = 0, ny = 0, L = 1, K = 4;
-  double h = 0, dt = 0, c0 = 1, alpha = 0, r = 0.5, gamma = 0.75;
-  double lam = 0, mu = 0;  // c0-scaled
-  double om_s = 0, om_d = 0, b_s = 0, b_d = 0, beta22 = 0, kD = 0, cstar = 0;
-  double omf_u = 1.0;
-  bool het = false, has_body = false, has_src = false;
-  int el[4] = {0, 0, 0, 0};
-  int ne_fixed = 3, ne_max = 50;
-  double ne_tol = 0;
-  // device pointers
-  void* f[2] = {nullptr, nullptr};
-  double* D[3] = {nullptr, nullptr, nullptr};
-  double *pout = nullptr, *fbody = nullptr, *src = nullptr, *omf = nullptr;
-  void *Ft = nullptr, *eref = nullptr, *pref = nullptr;
-  double *eta = nullptr, *sig = nullptr, *part = nullptr, *scal = nullptr;
-  int *phase = nullptr, *flags = nullptr;
-  double* elbc[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool elbc_used[4] = {false, false, false, false};
-  int8_t* ftype[4] = {nullptr, nullptr, nullptr, nullptr};
-  double* flbc[4] = {nullptr, nullptr, nullptr, nullptr};
-  // host state
-  int step = 0;
-  int64_t total_cycles = 0;
-  int last_ne = 0;
-  double last_ratio = -1.0;
-  bp_status status = BP_OK;
-  hipGraphExec_t graph = nullptr;
-  bool graph_valid = false;
-  double* host_pin = nullptr;  // pinned 4 doubles
-  bool use_graph = true;
-};
-
-namespace {
-
-template <typename T> ElConst<T> el_const(const bp_solver* s) {
-  ElConst<T> k;
-  k.om_s = T(s->om_s);
-  k.om_d = T(s->om_d);
-  k.beta22 = T(s->beta22);
-  k.kD = T(s->kD);
-  k.cstar = T(s->cstar);
-  k.gamma = T(s->gamma);
-  return k;
+// bytes of the engine's own area (descriptors and work lists) for a set of
+// problems
+// entries this problem adds to the engine's tile lists (see engine_upload):
+// every level in the full set, every level but the coarsest in the
+// restriction set, the finest level again for the flow step, and the
+// finest level's cell blocks
+size_t tile_entries_for(const Layout& lo) {
+  size_t t = 0;
+  for (int l = 1; l <= lo.L; ++l) t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * (l >= 2 ? 2 : 1);
+  t += (size_t)sweep_tiles(lo.nx, lo.ny);
+  t += (size_t)cell_blocks(lo.nx, lo.ny);
+  return t;
 }
 
-// one sweep on level l; the instantiation follows the level's storage and its
-// coarser neighbour's storage
-struct SweepReq {
-  int l;
-  int mode;
-  const void* in;
-  void* out;
-  const void* r;
-  const void* Ft;
-  const void* e;   // coarse correction (level l-1 storage)
-  void* rc;        // coarse rhs (level l-1 storage)
-  bool zero_g;
-  double* partials;
-};
-
-template <typename T, typename Tc, bool SHIFT>
-bp_status sweep_t(bp_solver* s, const SweepReq& q) {
-  const LevelBuf& v = s->lo.lv[q.l];
-  SweepArgs<T, Tc> a{};
-  a.g = (const T*)q.in;
-  a.out = (T*)q.out;
-  a.r = (const T*)q.r;
-  a.Ft = (const T*)q.Ft;
-  a.e = (const Tc*)q.e;
-  a.rc = (Tc*)q.rc;
-  a.eref = SHIFT ? (const T*)s->eref : nullptr;
-  a.partials = q.partials;
-  a.nx = v.nx;
-  a.ny = v.ny;
-  a.pitch = v.pitch;
-  a.plane = v.plane;
-  if (q.l > 1) {
-    a.cpitch = s->lo.lv[q.l - 1].pitch;
-    a.cplane = s->lo.lv[q.l - 1].plane;
-  }
-  for (int k = 0; k < 4; ++k) {
-    a.el[k] = s->el[k];
-    a.bc[k] = (q.l == s->L && s->elbc_used[k]) ? s->elbc[k] : nullptr;
-  }
-  a.k = el_const<T>(s);
-  a.H = v.H;
-  a.zero_g = q.zero_g ? 1 : 0;
-  hipError_t e;
-  switch (q.mode) {
-    case kSmooth: e = launch_sweep<T, Tc, kSmooth, SHIFT>(a, s->stream); break;
-    case kRestrict: e = launch_sweep<T, Tc, kRestrict, SHIFT>(a, s->stream); break;
-    default: e = launch_sweep<T, Tc, kApply, SHIFT>(a, s->stream); break;
-  }
-  if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("sweep launch: ") + hipGetErrorString(e));
-  return BP_OK;
-}
-
-bp_status sweep(bp_solver* s, const SweepReq& q) {
-  const LevelBuf& v = s->lo.lv[q.l];
-  const bool cdbl = q.l > 1 ? s->lo.lv[q.l - 1].dbl : v.dbl;
-  const bool shift = s->lo.shift && q.l == s->L;
-  if (v.dbl) {
-    return shift ? sweep_t<double, double, true>(s, q) : sweep_t<double, double, false>(s, q);
-  }
-  if (cdbl) return shift ? sweep_t<float, double, true>(s, q) : sweep_t<float, double, false>(s, q);
-  return shift ? sweep_t<float, float, true>(s, q) : sweep_t<float, float, false>(s, q);
-}
-
-// ELASTIC_MULTIGRID (Algorithm 4) on level l.  The level's iterate starts in gA
-// (or is zero when zero_start) and ends in gA: 2K smoothing writes alternate
-// between gA and gB.  When first_done, the first pre-smoothing sweep has
-// already been run (its result is in gB).
-bp_status vcycle(bp_solver* s, int l, bool zero_start, bool first_done, double* last_partials) {
-  LevelBuf& v = s->lo.lv[l];
-  const bool fine = (l == s->L);
-  const void* Ft = fine ? s->Ft : nullptr;
-  const void* r = fine ? nullptr : v.r;
-  void* cur = v.gA;
-  void* alt = v.gB;
-  for (int k = 0; k < s->K; ++k) {
-    if (!(k == 0 && first_done)) {
-      BPCHK(sweep(s, SweepReq{l, kSmooth, cur, alt, r, Ft, nullptr, nullptr, zero_start && k == 0, nullptr}));
-    }
-    std::swap(cur, alt);
-  }
-  const void* e = nullptr;
-  if (l > 1) {
-    LevelBuf& c = s->lo.lv[l - 1];
-    BPCHK(sweep(s, SweepReq{l, kRestrict, cur, nullptr, r, Ft, nullptr, c.r, false, fine ? last_partials : nullptr}));
-    BPCHK(vcycle(s, l - 1, true, false, nullptr));
-    e = c.gA;
-  }
-  for (int k = 0; k < s->K; ++k) {
-    double* part = (fine && l == 1 && k == s->K - 1) ? last_partials : nullptr;
-    BPCHK(sweep(s, SweepReq{l, kSmooth, cur, alt, r, Ft, k == 0 ? e : nullptr, nullptr, false, part}));
-    std::swap(cur, alt);
-  }
-  return BP_OK;
-}
-
-template <typename T> bp_status launch_force_t(bp_solver* s) {
-  ForceArgs<T> a{};
-  a.fbuf[0] = (T*)s->f[0];
-  a.fbuf[1] = (T*)s->f[1];
-  for (int k = 0; k < 3; ++k) a.Dbuf[k] = s->D[k];
-  a.phase = s->phase;
-  a.fbody = s->has_body ? s->fbody : nullptr;
-  a.src = s->has_src ? s->src : nullptr;
-  a.omf = s->het ? s->omf : nullptr;
-  a.omf_u = s->omf_u;
-  a.alpha = s->alpha;
-  a.alpha_h = s->alpha / s->h;
-  a.h = s->h;
-  a.r = s->r;
-  a.Ft = (T*)s->Ft;
-  a.nx = s->nx;
-  a.ny = s->ny;
-  a.pitch = s->lo.pitch;
-  a.plane = s->lo.plane;
-  a.perx = s->el[kLeft] == kElPeriodic;
-  a.pery = s->el[kBottom] == kElPeriodic;
-  HIPCHK(launch_force<T>(a, s->stream));
-  return BP_OK;
-}
-
-bp_status run_force(bp_solver* s) { return s->lo.fdbl ? launch_force_t<double>(s) : launch_force_t<float>(s); }
-
-template <typename T, bool SHIFT> bp_status launch_flow_t(bp_solver* s) {
-  FlowArgs<T> a{};
-  a.fbuf[0] = (T*)s->f[0];
-  a.fbuf[1] = (T*)s->f[1];
-  a.g = (const T*)s->lo.lv[s->L].gA;
-  for (int k = 0; k < 3; ++k) a.Dbuf[k] = s->D[k];
-  a.phase = s->phase;
-  a.p_out = s->pout;
-  a.src = s->has_src ? s->src : nullptr;
-  a.omf = s->het ? s->omf : nullptr;
-  a.omf_u = s->omf_u;
-  a.alpha_h = s->alpha / s->h;
-  a.r = s->r;
-  a.kD = s->kD;
-  a.pref = SHIFT ? (T*)s->pref : nullptr;
-  a.nx = s->nx;
-  a.ny = s->ny;
-  a.pitch = s->lo.pitch;
-  a.plane = s->lo.plane;
-  for (int k = 0; k < 4; ++k) {
-    a.ftype[k] = s->ftype[k];
-    a.bc[k] = s->flbc[k];
-  }
-  a.H = s->lo.lv[s->L].H;
-  HIPCHK((launch_flow<T, SHIFT>(a, s->stream)));
-  return BP_OK;
-}
-
-bp_status run_flow(bp_solver* s) {
-  if (s->lo.fdbl) return s->lo.shift ? launch_flow_t<double, true>(s) : launch_flow_t<double, false>(s);
-  return s->lo.shift ? launch_flow_t<float, true>(s) : launch_flow_t<float, false>(s);
-}
-
-template <typename T> bp_status launch_rebase_t(bp_solver* s) {
-  RebaseArgs<T> a{};
-  a.fbuf[0] = (T*)s->f[0];
-  a.fbuf[1] = (T*)s->f[1];
-  a.phase = s->phase;
-  a.g = (T*)s->lo.lv[s->L].gA;
-  a.eref = (T*)s->eref;
-  a.pref = (T*)s->pref;
-  a.nx = s->nx;
-  a.ny = s->ny;
-  a.pitch = s->lo.pitch;
-  a.plane = s->lo.plane;
-  HIPCHK(launch_rebase<T>(a, s->stream));
-  return BP_OK;
-}
-
-bp_status run_rebase(bp_solver* s) { return s->lo.fdbl ? launch_rebase_t<double>(s) : launch_rebase_t<float>(s); }
-
-template <typename T> bp_status launch_init_t(bp_solver* s) {
-  InitArgs<T> a{};
-  a.fbuf[0] = (T*)s->f[0];
-  a.fbuf[1] = (T*)s->f[1];
-  a.g = (T*)s->lo.lv[s->L].gA;
-  for (int k = 0; k < 3; ++k) a.Dbuf[k] = s->D[k];
-  a.phase = s->phase;
-  a.fbody = s->has_body ? s->fbody : nullptr;
-  a.src = s->has_src ? s->src : nullptr;
-  a.eref = (T*)s->eref;
-  a.pref = (T*)s->pref;
-  a.p_out = s->pout;
-  a.nx = s->nx;
-  a.ny = s->ny;
-  a.pitch = s->lo.pitch;
-  a.plane = s->lo.plane;
-  HIPCHK(launch_init<T>(a, s->stream));
-  return BP_OK;
-}
-
-bp_status run_init(bp_solver* s) { return s->lo.fdbl ? launch_init_t<double>(s) : launch_init_t<float>(s); }
-
-template <typename T, bool SHIFT> bp_status launch_extract_t(bp_solver* s) {
-  ExtractArgs<T> a{};
-  a.g = (const T*)s->lo.lv[s->L].gA;
-  a.Ft = (const T*)s->Ft;
-  a.eref = SHIFT ? (const T*)s->eref : nullptr;
-  a.kD = s->kD;
-  a.cstar = s->cstar;
-  a.b_s = s->b_s;
-  a.b_d = s->b_d;
-  a.inv_c0h = 1.0 / (s->c0 * s->h);
-  a.eta = s->eta;
-  a.sigma = s->sig;
-  a.nx = s->nx;
-  a.ny = s->ny;
-  a.pitch = s->lo.pitch;
-  a.plane = s->lo.plane;
-  a.perx = s->el[kLeft] == kElPeriodic;
-  a.pery = s->el[kBottom] == kElPeriodic;
-  HIPCHK((launch_extract<T, SHIFT>(a, s->stream)));
-  return BP_OK;
-}
-
-bp_status run_extract(bp_solver* s) {
-  if (s->lo.fdbl) return s->lo.shift ? launch_extract_t<double, true>(s) : launch_extract_t<double, false>(s);
-  return s->lo.shift ? launch_extract_t<float, true>(s) : launch_extract_t<float, false>(s);
-}
-
-int fine_waves(const bp_solver* s) {
-  const LevelBuf& v = s->lo.lv[s->L];
-  return sweep_waves(v.nx, v.ny, v.H);
-}
-
-// the device work of one time step with a fixed number of V-cycles
-bp_status enqueue_fixed_step(bp_solver* s) {
-  if (s->lo.shift) BPCHK(run_rebase(s));
-  BPCHK(run_force(s));
-  for (int j = 0; j < s->ne_fixed; ++j) {
-    const bool last = (j == s->ne_fixed - 1);
-    BPCHK(vcycle(s, s->L, false, false, last ? s->part : nullptr));
-  }
-  if (s->ne_fixed > 0) HIPCHK(launch_finalize(s->part, fine_waves(s), s->scal, s->flags, s->stream));
-  BPCHK(run_flow(s));
-  HIPCHK(launch_advance(s->phase, s->stream));
-  return BP_OK;
-}
-
-bp_status build_graph(bp_solver* s) {
-  if (s->graph) {
-    (void)hipGraphExecDestroy(s->graph);
-    s->graph = nullptr;
-  }
-  s->graph_valid = false;
-  if (!s->use_graph || !s->stream) return BP_OK;
-  HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-  bp_status st = enqueue_fixed_step(s);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(s->stream, &g);
-  if (st != BP_OK) {
-    if (g) (void)hipGraphDestroy(g);
-    return st;
-  }
-  if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-  s->graph_valid = true;
-  return BP_OK;
-}
-
-// adaptive number of V-cycles: before V-cycle j+1 (j >= 1) the first smoothing
-// sweep also measures ||g - S(g)|| and ||g||; the cycle is abandoned (the
-// sweep's output discarded) once the ratio reaches the tolerance
-bp_status adaptive_step(bp_solver* s) {
-  if (s->lo.shift) BPCHK(run_rebase(s));
-  BPCHK(run_force(s));
-  LevelBuf& v = s->lo.lv[s->L];
-  int j = 0;
-  double ratio = -1.0;
-  for (;;) {
-    if (j >= 1) {
-      BPCHK(sweep(s, SweepReq{s->L, kSmooth, v.gA, v.gB, nullptr, s->Ft, nullptr, nullptr, false, s->part}));
-      HIPCHK(launch_finalize(s->part, fine_waves(s), s->scal, s->flags, s->stream));
-      HIPCHK(hipMemcpyAsync(s->host_pin, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(hipStreamSynchronize(s->stream));
-      const double nr = std::sqrt(s->host_pin[0]), ng = std::sqrt(s->host_pin[1]);
-      ratio = ng > 0 ? nr / ng : 0.0;
-      if (!std::isfinite(nr) || !std::isfinite(ng)) {
-        s->status = BP_ERR_DIVERGED;
-        return fail(BP_ERR_DIVERGED, "non-finite residual norm");
-      }
-      if (nr <= s->ne_tol * ng || j >= s->ne_max) break;
-      BPCHK(vcycle(s, s->L, false, true, nullptr));
-    } else {
-      BPCHK(vcycle(s, s->L, false, false, nullptr));
-    }
-    ++j;
-  }
-  s->last_ne = j;
-  s->last_ratio = ratio;
-  s->total_cycles += j;
-  BPCHK(run_flow(s));
-  HIPCHK(launch_advance(s->phase, s->stream));
-  return BP_OK;
+size_t engine_bytes(size_t nprobs, size_t tile_entries) {
+  return align_up(nprobs * sizeof(ProbD)) + align_up(tile_entries * sizeof(int2)) + align_up(nprobs * sizeof(int));
 }
 
 // ------------------------------------------------------- boundary terms
 // value of side data at the midpoint of the link leaving boundary cell i of
-// `side` in direction (ox, oy); see the corner rules in the header comment of
-// bp_create
+// `side` in direction (ox, oy).  Data are given at face centres; a diagonal
+// link ends at a corner point of the face, whose value is the mean of the two
+// face values beside it; at the end of a side the second value comes from the
+// perpendicular side: periodic wrap, the mirror image for a symmetry wall (the
+// component normal to the mirror changes sign), otherwise linear extrapolation.
 void link_value(const bp_problem* p, int side, int i, int ox, int oy, const double* vals, int ncomp,
                 double out[2]) {
   const int n = side_len(side, p->nx, p->ny);
@@ -583,8 +238,6 @@ void link_value(const bp_problem* p, int side, int i, int ox, int oy, const doub
       const int tw = ((t % n) + n) % n;
       for (int k = 0; k < ncomp; ++k) other[k] = vals ? vals[ncomp * tw + k] : 0.0;
     } else if (kind == 1) {
-      // mirror image across the perpendicular wall: the component normal to
-      // that wall changes sign (tangential index of this side's data)
       const int mc = xwall ? 1 : 0;
       for (int k = 0; k < ncomp; ++k) other[k] = (ncomp == 2 && k == mc) ? -out[k] : out[k];
     } else {
@@ -640,26 +293,45 @@ void flow_terms(const bp_problem* p, int side, std::vector<double>& out, std::ve
   }
 }
 
-// ------------------------------------------------------------ state I/O
+double geq_host(int q, double ex, double ey) { return 3.0 * W8[q] * (CX8[q] * ex + CY8[q] * ey); }
+
+// ------------------------------------------------------------- problems
+struct Prob {
+  Layout lo;
+  char* base = nullptr;
+  ProbD d{};  // host copy of the device descriptor
+  int nx = 0, ny = 0, L = 1, K = 4;
+  double h = 0, dt = 0, c0 = 1;
+  int ne_fixed = 3, ne_max = 50;
+  double ne_tol = 0;
+  bool has_body = false, has_src = false;
+  int step = 0;
+  int64_t total_cycles = 0;
+  int last_ne = 0;
+  double last_ratio = -1.0;
+  bp_status status = BP_OK;
+  int64_t user_id = -1;
+};
+
 template <typename T>
-bp_status upload_planes(bp_solver* s, void* dst, int nx, int ny, int pitch, int64_t plane, const double* src,
+bp_status upload_planes(hipStream_t st, void* dst, int nx, int ny, int pitch, int64_t plane, const double* src,
                         int m) {
   std::vector<T> tmp((size_t)m * plane, T(0));
   for (int c = 0; c < m; ++c)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x)
         tmp[(size_t)c * plane + (size_t)y * pitch + x] = src ? T(src[((size_t)c * ny + y) * nx + x]) : T(0);
-  HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
   return BP_OK;
 }
 
 template <typename T>
-bp_status download_planes(bp_solver* s, const void* srcd, int nx, int ny, int pitch, int64_t plane, double* dst,
+bp_status download_planes(hipStream_t st, const void* srcd, int nx, int ny, int pitch, int64_t plane, double* dst,
                           int m) {
   std::vector<T> tmp((size_t)m * plane);
-  HIPCHK(hipMemcpyAsync(tmp.data(), srcd, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
+  HIPCHK(hipMemcpyAsync(tmp.data(), srcd, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   for (int c = 0; c < m; ++c)
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x)
@@ -667,36 +339,537 @@ bp_status download_planes(bp_solver* s, const void* srcd, int nx, int ny, int pi
   return BP_OK;
 }
 
-bp_status up(bp_solver* s, bool dbl, void* dst, int nx, int ny, int pitch, int64_t plane, const double* src, int m) {
-  return dbl ? upload_planes<double>(s, dst, nx, ny, pitch, plane, src, m)
-             : upload_planes<float>(s, dst, nx, ny, pitch, plane, src, m);
+bp_status up(hipStream_t st, bool dbl, void* dst, int nx, int ny, int pitch, int64_t plane, const double* src, int m) {
+  return dbl ? upload_planes<double>(st, dst, nx, ny, pitch, plane, src, m)
+             : upload_planes<float>(st, dst, nx, ny, pitch, plane, src, m);
 }
-bp_status down(bp_solver* s, bool dbl, const void* srcd, int nx, int ny, int pitch, int64_t plane, double* dst,
+bp_status down(hipStream_t st, bool dbl, const void* srcd, int nx, int ny, int pitch, int64_t plane, double* dst,
                int m) {
-  return dbl ? download_planes<double>(s, srcd, nx, ny, pitch, plane, dst, m)
-             : download_planes<float>(s, srcd, nx, ny, pitch, plane, dst, m);
+  return dbl ? download_planes<double>(st, srcd, nx, ny, pitch, plane, dst, m)
+             : download_planes<float>(st, srcd, nx, ny, pitch, plane, dst, m);
 }
 
-bp_status upload_loads(bp_solver* s, const double* body_f, const double* source_s) {
-  const int nx = s->nx, ny = s->ny;
+bp_status upload_loads(hipStream_t st, Prob& P, const double* body_f, const double* source_s) {
+  const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
-  s->has_body = body_f != nullptr;
-  s->has_src = source_s != nullptr;
+  P.has_body = body_f != nullptr;
+  P.has_src = source_s != nullptr;
   std::vector<double> b(2 * N), sv(N);
   if (body_f)
-    for (size_t k = 0; k < 2 * N; ++k) b[k] = s->h * s->h * s->c0 * body_f[k];
+    for (size_t k = 0; k < 2 * N; ++k) b[k] = P.h * P.h * P.c0 * body_f[k];
   if (source_s)
-    for (size_t k = 0; k < N; ++k) sv[k] = s->dt * source_s[k];
-  BPCHK(upload_planes<double>(s, s->fbody, nx, ny, s->lo.pitch, s->lo.plane, body_f ? b.data() : nullptr, 2));
-  BPCHK(upload_planes<double>(s, s->src, nx, ny, s->lo.pitch, s->lo.plane, source_s ? sv.data() : nullptr, 1));
+    for (size_t k = 0; k < N; ++k) sv[k] = P.dt * source_s[k];
+  BPCHK(upload_planes<double>(st, P.base + P.lo.off_fbody, nx, ny, P.lo.pitch, P.lo.plane, body_f ? b.data() : nullptr, 2));
+  BPCHK(upload_planes<double>(st, P.base + P.lo.off_src, nx, ny, P.lo.pitch, P.lo.plane, source_s ? sv.data() : nullptr, 1));
+  P.d.fbody = P.has_body ? (const double*)(P.base + P.lo.off_fbody) : nullptr;
+  P.d.src = P.has_src ? (const double*)(P.base + P.lo.off_src) : nullptr;
   return BP_OK;
 }
 
-double geq_host(int q, double ex, double ey) { return 3.0 * W8[q] * (CX8[q] * ex + CY8[q] * ey); }
+// set up one problem inside device memory at `base` (layout lo already made)
+bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipStream_t st, Prob& P) {
+  P.lo = lo;
+  P.base = base;
+  P.nx = p->nx;
+  P.ny = p->ny;
+  P.L = lo.L;
+  P.K = p->K;
+  P.h = p->dx;
+  P.dt = p->dt;
+  P.c0 = p->c0;
+  P.ne_fixed = p->ne_fixed;
+  P.ne_tol = p->ne_tol;
+  P.ne_max = p->ne_max;
+  ProbD& d = P.d;
+  std::memset(&d, 0, sizeof(d));
+  d.L = lo.L;
+  for (int l = 1; l <= lo.L; ++l) {
+    const LevelLay& v = lo.lv[l];
+    d.lv[l].gA = base + v.oA;
+    d.lv[l].gB = base + v.oB;
+    d.lv[l].r = v.oR == SIZE_MAX ? nullptr : (void*)(base + v.oR);
+    d.lv[l].nx = v.nx;
+    d.lv[l].ny = v.ny;
+    d.lv[l].pitch = v.pitch;
+    d.lv[l].tiles_x = sweep_tiles_x(v.nx);
+    d.lv[l].plane = v.plane;
+  }
+  const double lam = p->c0 * p->lambda, mu = p->c0 * p->mu, lm = lam + mu;
+  d.om_s = 2.0 / (3.0 * lm + 1.0);            // Table 2
+  d.om_d = 2.0 / (6.0 * mu + 1.0);
+  d.b_s = 3.0 * lm / (3.0 * lm + 1.0);        // eq. moments:bared
+  d.b_d = 6.0 * mu / (6.0 * mu + 1.0);
+  d.beta22 = 1.0 / (12.0 * lm + 4.0);         // eq. moments:collision:22
+  d.kD = -d.b_s / (2.0 * lm);                 // eq. LBM:divergence
+  d.cstar = p->r * p->alpha * p->alpha / 2.0; // implicit part of the centred source
+  d.gamma = p->gamma;
+  d.alpha = p->alpha;
+  d.alpha_h = p->alpha / p->dx;
+  d.h = p->dx;
+  d.r = p->r;
+  d.inv_c0h = 1.0 / (p->c0 * p->dx);
+  for (int k = 0; k < 4; ++k) d.el[k] = p->side[k].el;
+  d.f[0] = base + lo.off_f[0];
+  d.f[1] = base + lo.off_f[1];
+  for (int k = 0; k < 3; ++k) d.D[k] = (double*)(base + lo.off_D[k]);
+  d.pout = (double*)(base + lo.off_pout);
+  d.Ft = base + lo.off_Ft;
+  d.eref = lo.shift ? (void*)(base + lo.off_eref) : nullptr;
+  d.pref = lo.shift ? (void*)(base + lo.off_pref) : nullptr;
+  d.eta = (double*)(base + lo.off_eta);
+  d.sig = (double*)(base + lo.off_sig);
+  d.partials = (double*)(base + lo.off_part);
+  d.norm2 = (double*)(base + lo.off_scal);
+  d.phase = (int*)(base + lo.off_scal + 32);
+  d.flags = (int*)(base + lo.off_scal + 40);
+  d.ntiles_fine = lo.ntiles_fine;
+  HIPCHK(launch_fill_zero(base, lo.total, st));
+
+  // permeability -> lattice relaxation rate of the flow LBM (eq. pressure:rate)
+  const size_t N = (size_t)p->nx * p->ny;
+  auto omega_of = [&](double kap) { return 1.0 / (3.0 * (kap / p->c0) * p->dt / (p->dx * p->dx) + 0.5); };
+  if (p->kappa) {
+    std::vector<double> om(N);
+    for (size_t k = 0; k < N; ++k) {
+      if (!(p->kappa[k] > 0)) return fail(BP_ERR_ARG, "kappa must be > 0 everywhere");
+      om[k] = omega_of(p->kappa[k]);
+    }
+    BPCHK(upload_planes<double>(st, base + lo.off_omf, p->nx, p->ny, lo.pitch, lo.plane, om.data(), 1));
+    d.omf = (const double*)(base + lo.off_omf);
+    d.omf_u = om[0];
+  } else {
+    d.omf = nullptr;
+    d.omf_u = omega_of(p->kappa_uniform);
+  }
+  for (int k = 0; k < 4; ++k) {
+    std::vector<double> et, ft;
+    std::vector<int8_t> ty;
+    elastic_terms(p, k, p->dx, et);
+    flow_terms(p, k, ft, ty);
+    double* elbc = (double*)(base + lo.off_elbc[k]);
+    int8_t* ftype = (int8_t*)(base + lo.off_ftype[k]);
+    double* flbc = (double*)(base + lo.off_flbc[k]);
+    HIPCHK(hipMemcpyAsync(elbc, et.data(), et.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(flbc, ft.data(), ft.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ftype, ty.data(), ty.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const bool used = (p->side[k].el == BP_EL_DIRICHLET || p->side[k].el == BP_EL_TRACTION);
+    d.elbc[k] = used ? elbc : nullptr;
+    d.ftype[k] = ftype;
+    d.flbc[k] = flbc;
+  }
+  BPCHK(upload_loads(st, P, p->body_f, p->source_s));
+  return BP_OK;
+}
+
+// ---------------------------------------------------------------- engine
+enum OpKind { OP_SWEEP, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+
+struct Op {
+  OpKind kind;
+  int mode = 0;           // sweep mode
+  int tdbl = 0, cdbl = 0; // sweep storage types (level, coarser level)
+  bool shift = false;
+  SweepL sw{};
+  CellL cl{};
+  ProbL pl{};
+  int count = 0;          // tiles / problems
+};
+
+// tile-list key of a depth: full set or restriction set, one of three
+// storage groups (level FP32 / coarser FP32, FP32 / FP64, FP64 / FP64)
+struct DepthLists {
+  int off[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  int cnt[2][3] = {{0, 0, 0}, {0, 0, 0}};
+};
+
+struct Engine {
+  hipStream_t stream = nullptr;
+  bool fdbl = true, shift = false;
+  int K = 4, ne = 3, maxL = 1;
+  std::vector<Prob*> probs;
+  // engine area (device): descriptors, tile lists, problem ids
+  char* area = nullptr;
+  size_t area_bytes = 0;
+  ProbD* d_probs = nullptr;
+  int2* d_tiles = nullptr;
+  int* d_pids = nullptr;
+  size_t tiles_cap = 0, probs_cap = 0;
+  std::vector<DepthLists> depth;  // per depth
+  int fine_off = 0, fine_cnt = 0; // depth-0 full-set tiles of every problem (flow)
+  int cell_off = 0, cell_cnt = 0; // finest-level cell blocks
+  std::vector<Op> step_ops;
+  hipGraphExec_t graph = nullptr;
+  bool graph_valid = false, use_graph = true;
+  double* host_pin = nullptr;
+};
+
+int tgroup(const Engine& E, const Prob& P, int depth) {
+  if (E.fdbl) return 2;
+  const int l = P.L - depth;
+  if (l == 1 && P.L > 1) return 2;      // FP64 coarsest level
+  if (l == 2) return 1;                 // FP32 level with an FP64 coarser level
+  return 0;
+}
+
+// write descriptors and tile lists for the current problem set
+bp_status engine_upload(Engine& E) {
+  const size_t np = E.probs.size();
+  if (np > E.probs_cap) return fail(BP_ERR_WORKSPACE, "too many problems for the engine area");
+  std::vector<ProbD> pd(np);
+  for (size_t i = 0; i < np; ++i) pd[i] = E.probs[i]->d;
+  E.maxL = 1;
+  for (auto* P : E.probs) E.maxL = std::max(E.maxL, P->L);
+  std::vector<int2> tiles;
+  E.depth.assign(E.maxL, DepthLists());
+  for (int d = 0; d < E.maxL; ++d) {
+    for (int set = 0; set < 2; ++set)
+      for (int g = 0; g < 3; ++g) {
+        E.depth[d].off[set][g] = (int)tiles.size();
+        for (size_t i = 0; i < np; ++i) {
+          const Prob& P = *E.probs[i];
+          const int l = P.L - d;
+          if (l < 1 || (set == 1 && l < 2) || tgroup(E, P, d) != g) continue;
+          const int nt = sweep_tiles(P.lo.lv[l].nx, P.lo.lv[l].ny);
+          for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
+        }
+        E.depth[d].cnt[set][g] = (int)tiles.size() - E.depth[d].off[set][g];
+      }
+  }
+  E.fine_off = (int)tiles.size();
+  for (size_t i = 0; i < np; ++i) {
+    const Prob& P = *E.probs[i];
+    const int nt = sweep_tiles(P.nx, P.ny);
+    for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
+  }
+  E.fine_cnt = (int)tiles.size() - E.fine_off;
+  E.cell_off = (int)tiles.size();
+  for (size_t i = 0; i < np; ++i) {
+    const Prob& P = *E.probs[i];
+    const int nb = cell_blocks(P.nx, P.ny);
+    for (int b = 0; b < nb; ++b) tiles.push_back(make_int2((int)i, b));
+  }
+  E.cell_cnt = (int)tiles.size() - E.cell_off;
+  if (tiles.size() > E.tiles_cap) return fail(BP_ERR_WORKSPACE, "tile lists exceed the engine area");
+  std::vector<int> pids(np);
+  for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
+  if (np) {
+    HIPCHK(hipMemcpyAsync(E.d_probs, pd.data(), np * sizeof(ProbD), hipMemcpyHostToDevice, E.stream));
+    HIPCHK(hipMemcpyAsync(E.d_pids, pids.data(), np * sizeof(int), hipMemcpyHostToDevice, E.stream));
+  }
+  if (!tiles.empty())
+    HIPCHK(hipMemcpyAsync(E.d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  E.graph_valid = false;
+  return BP_OK;
+}
+
+void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int in_sel, int out_sel, int prolong,
+                int partials) {
+  for (int g = 0; g < 3; ++g) {
+    const int cnt = E.depth[d].cnt[set][g];
+    if (cnt == 0) continue;
+    Op o;
+    o.kind = OP_SWEEP;
+    o.mode = mode;
+    o.tdbl = g == 2;
+    o.cdbl = g >= 1;
+    o.shift = E.shift && d == 0;
+    o.sw.probs = E.d_probs;
+    o.sw.tiles = E.d_tiles + E.depth[d].off[set][g];
+    o.sw.depth = d;
+    o.sw.in_sel = in_sel;
+    o.sw.out_sel = out_sel;
+    o.sw.prolong = prolong;
+    o.sw.partials = partials;
+    o.count = cnt;
+    ops.push_back(o);
+  }
+}
+
+// Algorithm 4 at depth d for every problem that has a level there.  The
+// iterate of a level starts in buffer A (zero at coarse depths) and ends in A
+// after its 2K smoothing sweeps.  first_done: the first pre-smoothing sweep
+// was already issued (adaptive mode).
+void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last) {
+  int sel = 0;
+  for (int k = 0; k < E.K; ++k) {
+    if (!(k == 0 && first_done)) add_sweeps(E, ops, d, 0, kSmooth, (d > 0 && k == 0) ? 2 : sel, 1 - sel, 0, 0);
+    sel = 1 - sel;
+  }
+  bool deeper = false;
+  for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[1][g] > 0;
+  if (deeper) {
+    add_sweeps(E, ops, d, 1, kRestrict, sel, 0, 0, 0);
+    add_vcycle(E, ops, d + 1, false, false);
+  }
+  for (int k = 0; k < E.K; ++k) {
+    const int part = (partials_last && d == 0 && k == E.K - 1) ? 1 : 0;
+    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, part);
+    sel = 1 - sel;
+  }
+}
+
+Op cell_op(Engine& E, OpKind k) {
+  Op o;
+  o.kind = k;
+  o.cl.probs = E.d_probs;
+  o.cl.tiles = E.d_tiles + E.cell_off;
+  o.count = E.cell_cnt;
+  return o;
+}
+Op prob_op(Engine& E, OpKind k) {
+  Op o;
+  o.kind = k;
+  o.pl.probs = E.d_probs;
+  o.pl.pids = E.d_pids;
+  o.count = (int)E.probs.size();
+  return o;
+}
+Op flow_op(Engine& E) {
+  Op o;
+  o.kind = OP_FLOW;
+  o.cl.probs = E.d_probs;
+  o.cl.tiles = E.d_tiles + E.fine_off;
+  o.count = E.fine_cnt;
+  return o;
+}
+
+void build_step_ops(Engine& E) {
+  std::vector<Op>& ops = E.step_ops;
+  ops.clear();
+  if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
+  ops.push_back(cell_op(E, OP_FORCE));
+  for (int j = 0; j < E.ne; ++j) add_vcycle(E, ops, 0, false, j == E.ne - 1);
+  if (E.ne > 0) ops.push_back(prob_op(E, OP_FINALIZE));
+  ops.push_back(flow_op(E));
+  ops.push_back(prob_op(E, OP_ADVANCE));
+}
+
+template <typename T, typename Tc>
+hipError_t sweep_launch(const Op& o, hipStream_t s) {
+  if (o.shift) {
+    switch (o.mode) {
+      case kSmooth: return launch_tsweep<T, Tc, kSmooth, true>(o.sw, o.count, s);
+      case kRestrict: return launch_tsweep<T, Tc, kRestrict, true>(o.sw, o.count, s);
+      default: return launch_tsweep<T, Tc, kApply, true>(o.sw, o.count, s);
+    }
+  }
+  switch (o.mode) {
+    case kSmooth: return launch_tsweep<T, Tc, kSmooth, false>(o.sw, o.count, s);
+    case kRestrict: return launch_tsweep<T, Tc, kRestrict, false>(o.sw, o.count, s);
+    default: return launch_tsweep<T, Tc, kApply, false>(o.sw, o.count, s);
+  }
+}
+
+hipError_t run_op(const Engine& E, const Op& o) {
+  hipStream_t s = E.stream;
+  switch (o.kind) {
+    case OP_SWEEP:
+      if (o.tdbl) return sweep_launch<double, double>(o, s);
+      if (o.cdbl) return sweep_launch<float, double>(o, s);
+      return sweep_launch<float, float>(o, s);
+    case OP_FORCE: return E.fdbl ? launch_force<double>(o.cl, o.count, s) : launch_force<float>(o.cl, o.count, s);
+    case OP_REBASE: return E.fdbl ? launch_rebase<double>(o.cl, o.count, s) : launch_rebase<float>(o.cl, o.count, s);
+    case OP_INIT: return E.fdbl ? launch_init<double>(o.cl, o.count, s) : launch_init<float>(o.cl, o.count, s);
+    case OP_FLOW:
+      if (E.fdbl) return E.shift ? launch_tflow<double, true>(o.cl, o.count, s) : launch_tflow<double, false>(o.cl, o.count, s);
+      return E.shift ? launch_tflow<float, true>(o.cl, o.count, s) : launch_tflow<float, false>(o.cl, o.count, s);
+    case OP_EXTRACT:
+      if (E.fdbl) return E.shift ? launch_extract<double, true>(o.cl, o.count, s) : launch_extract<double, false>(o.cl, o.count, s);
+      return E.shift ? launch_extract<float, true>(o.cl, o.count, s) : launch_extract<float, false>(o.cl, o.count, s);
+    case OP_FINALIZE: return launch_finalize(o.pl, o.count, s);
+    case OP_ADVANCE: return launch_advance(o.pl, o.count, s);
+  }
+  return hipSuccess;
+}
+
+bp_status run_ops(const Engine& E, const std::vector<Op>& ops) {
+  for (const Op& o : ops) {
+    hipError_t e = run_op(E, o);
+    if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  return BP_OK;
+}
+
+bp_status build_graph(Engine& E) {
+  if (E.graph) {
+    (void)hipGraphExecDestroy(E.graph);
+    E.graph = nullptr;
+  }
+  E.graph_valid = false;
+  build_step_ops(E);
+  if (!E.use_graph || !E.stream) {
+    E.graph_valid = true;
+    return BP_OK;
+  }
+  HIPCHK(hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal));
+  bp_status st = run_ops(E, E.step_ops);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(E.stream, &g);
+  if (st != BP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&E.graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  E.graph_valid = true;
+  return BP_OK;
+}
+
+bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap, size_t tiles_cap, hipStream_t st,
+                      bool fdbl, bool shift, int K, int ne) {
+  E.stream = st;
+  E.area = area;
+  E.area_bytes = area_bytes;
+  E.probs_cap = probs_cap;
+  E.tiles_cap = tiles_cap;
+  E.d_probs = (ProbD*)area;
+  E.d_tiles = (int2*)(area + align_up(probs_cap * sizeof(ProbD)));
+  E.d_pids = (int*)((char*)E.d_tiles + align_up(tiles_cap * sizeof(int2)));
+  E.fdbl = fdbl;
+  E.shift = shift;
+  E.K = K;
+  E.ne = ne;
+  if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
+  if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
+  return BP_OK;
+}
+
+void engine_release(Engine& E) {
+  if (E.graph) (void)hipGraphExecDestroy(E.graph);
+  E.graph = nullptr;
+  if (E.host_pin) (void)hipHostFree(E.host_pin);
+  E.host_pin = nullptr;
+}
+
+// one time step of every problem of the engine with a fixed number of
+// V-cycles: a captured HIP graph when a stream is given, else direct launches
+bp_status fixed_step(Engine& E) {
+  if (!E.graph_valid) BPCHK(build_graph(E));
+  if (E.graph) {
+    HIPCHK(hipGraphLaunch(E.graph, E.stream));
+  } else {
+    BPCHK(run_ops(E, E.step_ops));
+  }
+  for (auto* P : E.probs) {
+    P->step += 1;
+    P->last_ne = E.ne;
+    P->total_cycles += E.ne;
+  }
+  return BP_OK;
+}
+
+// adaptive number of V-cycles (single-problem engines): before V-cycle j+1
+// (j >= 1) the first smoothing sweep also measures ||g - S(g)|| and ||g||; the
+// cycle is abandoned (the sweep's output discarded) once the ratio reaches the
+// tolerance
+bp_status adaptive_step(Engine& E) {
+  Prob& P = *E.probs[0];
+  std::vector<Op> ops;
+  if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
+  ops.push_back(cell_op(E, OP_FORCE));
+  BPCHK(run_ops(E, ops));
+  int j = 0;
+  double ratio = -1.0;
+  for (;;) {
+    ops.clear();
+    if (j >= 1) {
+      add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 1);
+      ops.push_back(prob_op(E, OP_FINALIZE));
+      BPCHK(run_ops(E, ops));
+      HIPCHK(hipMemcpyAsync(E.host_pin, P.d.norm2, 2 * sizeof(double), hipMemcpyDeviceToHost, E.stream));
+      HIPCHK(hipStreamSynchronize(E.stream));
+      const double nr = std::sqrt(E.host_pin[0]), ng = std::sqrt(E.host_pin[1]);
+      ratio = ng > 0 ? nr / ng : 0.0;
+      if (!std::isfinite(nr) || !std::isfinite(ng)) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
+      if (nr <= P.ne_tol * ng || j >= P.ne_max) break;
+      ops.clear();
+      add_vcycle(E, ops, 0, true, false);
+      BPCHK(run_ops(E, ops));
+    } else {
+      add_vcycle(E, ops, 0, false, false);
+      BPCHK(run_ops(E, ops));
+    }
+    ++j;
+  }
+  P.last_ne = j;
+  P.last_ratio = ratio;
+  P.total_cycles += j;
+  ops.clear();
+  ops.push_back(flow_op(E));
+  ops.push_back(prob_op(E, OP_ADVANCE));
+  BPCHK(run_ops(E, ops));
+  P.step += 1;
+  return BP_OK;
+}
+
+bp_status init_states(Engine& E) {
+  std::vector<Op> ops{cell_op(E, OP_INIT)};
+  BPCHK(run_ops(E, ops));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  for (auto* P : E.probs) {
+    P->step = 0;
+    P->status = BP_OK;
+  }
+  return BP_OK;
+}
+
+bp_status extract_fields(Engine& E) {
+  std::vector<Op> ops{cell_op(E, OP_EXTRACT)};
+  return run_ops(E, ops);
+}
+
+bp_status fields_of(Engine& E, Prob& P, double* eta, double* p, double* sigma, int32_t* step) {
+  const size_t N = (size_t)P.nx * P.ny;
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, P.d.flags, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  if (eta) HIPCHK(hipMemcpyAsync(eta, P.d.eta, 2 * N * 8, hipMemcpyDeviceToHost, E.stream));
+  if (sigma) HIPCHK(hipMemcpyAsync(sigma, P.d.sig, 3 * N * 8, hipMemcpyDeviceToHost, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  if (p) {
+    BPCHK(download_planes<double>(E.stream, P.d.pout, P.nx, P.ny, P.lo.pitch, P.lo.plane, p, 1));
+    for (size_t k = 0; k < N; ++k) p[k] /= P.c0;
+  }
+  if (step) *step = P.step;
+  bool finite = true;
+  if (eta)
+    for (size_t k = 0; k < 2 * N && finite; ++k) finite = std::isfinite(eta[k]);
+  if (flag || !finite) {
+    P.status = BP_ERR_DIVERGED;
+    return fail(BP_ERR_DIVERGED, "the solution is not finite");
+  }
+  return BP_OK;
+}
 
 }  // namespace
 
-// ===================================================================== C ABI
+// ===================================================================== solver
+struct bp_solver {
+  Engine E;
+  Prob P;
+  char* ws = nullptr;
+};
+
+struct bp_batch {
+  Engine E;
+  std::vector<Prob> P;
+};
+
+namespace {
+
+// one application on one level of a single-problem engine: buffer A -> B
+bp_status single_apply(bp_solver* s, int level) {
+  std::vector<Op> ops;
+  add_sweeps(s->E, ops, s->P.L - level, 0, kApply, 0, 1, 0, 0);
+  return run_ops(s->E, ops);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bp_last_error(void) { return g_err.c_str(); }
@@ -706,7 +879,7 @@ bp_status bp_workspace_bytes(const bp_problem* p, size_t* device_bytes) {
   if (!device_bytes) return fail(BP_ERR_ARG, "null output");
   Layout lo;
   make_layout(p, lo);
-  *device_bytes = lo.total;
+  *device_bytes = lo.total + engine_bytes(1, tile_entries_for(lo));
   return BP_OK;
 }
 
@@ -716,211 +889,98 @@ bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void*
   BPCHK(validate(p));
   Layout lo;
   make_layout(p, lo);
-  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0 || ws_bytes < lo.total)
+  const size_t te = tile_entries_for(lo);
+  const size_t need = lo.total + engine_bytes(1, te);
+  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0 || ws_bytes < need)
     return fail(BP_ERR_WORKSPACE, "workspace missing, not 256-byte aligned or smaller than bp_workspace_bytes");
   bp_solver* s = new bp_solver();
-  s->lo = lo;
-  s->stream = (hipStream_t)hip_stream;
-  s->ws = (char*)device_ws;
-  s->nx = p->nx;
-  s->ny = p->ny;
-  s->L = lo.L;
-  s->K = p->K;
-  s->h = p->dx;
-  s->dt = p->dt;
-  s->c0 = p->c0;
-  s->alpha = p->alpha;
-  s->r = p->r;
-  s->gamma = p->gamma;
-  s->lam = p->c0 * p->lambda;
-  s->mu = p->c0 * p->mu;
-  const double lm = s->lam + s->mu;
-  s->om_s = 2.0 / (3.0 * lm + 1.0);            // Table 2
-  s->om_d = 2.0 / (6.0 * s->mu + 1.0);
-  s->b_s = 3.0 * lm / (3.0 * lm + 1.0);        // eq. moments:bared
-  s->b_d = 6.0 * s->mu / (6.0 * s->mu + 1.0);
-  s->beta22 = 1.0 / (12.0 * lm + 4.0);         // eq. moments:collision:22
-  s->kD = -s->b_s / (2.0 * lm);                // eq. LBM:divergence
-  s->cstar = s->r * s->alpha * s->alpha / 2.0; // implicit part of the centred source
-  s->ne_fixed = p->ne_fixed;
-  s->ne_tol = p->ne_tol;
-  s->ne_max = p->ne_max;
-  for (int k = 0; k < 4; ++k) s->el[k] = p->side[k].el;
-  char* w = s->ws;
-  for (int l = 1; l <= lo.L; ++l) {
-    LevelBuf& v = s->lo.lv[l];
-    v.gA = w + v.oA;
-    v.gB = w + v.oB;
-    v.r = v.oR ? (void*)(w + v.oR) : nullptr;
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* w = (char*)device_ws;
+  s->ws = w;
+  bp_status rc = engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed);
+  if (rc == BP_OK) rc = setup_problem(p, lo, w, st, s->P);
+  if (rc == BP_OK) {
+    s->E.probs = {&s->P};
+    rc = engine_upload(s->E);
   }
-  s->f[0] = w + lo.off_f[0];
-  s->f[1] = w + lo.off_f[1];
-  for (int k = 0; k < 3; ++k) s->D[k] = (double*)(w + lo.off_D[k]);
-  s->pout = (double*)(w + lo.off_pout);
-  s->fbody = (double*)(w + lo.off_fbody);
-  s->src = (double*)(w + lo.off_src);
-  s->omf = (double*)(w + lo.off_omf);
-  s->Ft = w + lo.off_Ft;
-  s->eref = lo.shift ? (void*)(w + lo.off_eref) : nullptr;
-  s->pref = lo.shift ? (void*)(w + lo.off_pref) : nullptr;
-  s->eta = (double*)(w + lo.off_eta);
-  s->sig = (double*)(w + lo.off_sig);
-  s->part = (double*)(w + lo.off_part);
-  s->scal = (double*)(w + lo.off_scal);
-  s->phase = (int*)(w + lo.off_scal + 32);
-  s->flags = (int*)(w + lo.off_scal + 40);
-
-  auto bail = [&](bp_status st) {
+  if (rc == BP_OK) rc = init_states(s->E);
+  if (rc != BP_OK) {
+    engine_release(s->E);
     delete s;
-    return st;
-  };
-  if (hipHostMalloc((void**)&s->host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return bail(fail(BP_ERR_DEVICE, "hipHostMalloc failed"));
-  if (launch_fill_zero(w, lo.total, s->stream) != hipSuccess) return bail(fail(BP_ERR_DEVICE, "clear failed"));
-
-  // permeability -> lattice relaxation rate of the flow LBM (eq. pressure:rate)
-  const size_t N = (size_t)p->nx * p->ny;
-  auto omega_of = [&](double kap) { return 1.0 / (3.0 * (kap / p->c0) * p->dt / (p->dx * p->dx) + 0.5); };
-  if (p->kappa) {
-    std::vector<double> om(N);
-    for (size_t k = 0; k < N; ++k) {
-      if (!(p->kappa[k] > 0)) return bail(fail(BP_ERR_ARG, "kappa must be > 0 everywhere"));
-      om[k] = omega_of(p->kappa[k]);
-    }
-    s->het = true;
-    s->omf_u = om[0];
-    if (upload_planes<double>(s, s->omf, p->nx, p->ny, lo.pitch, lo.plane, om.data(), 1) != BP_OK)
-      return bail(BP_ERR_DEVICE);
-  } else {
-    s->het = false;
-    s->omf_u = omega_of(p->kappa_uniform);
+    return rc;
   }
-  // boundary terms (finest level; coarse levels use homogeneous data)
-  for (int k = 0; k < 4; ++k) {
-    std::vector<double> et, ft;
-    std::vector<int8_t> ty;
-    elastic_terms(p, k, s->h, et);
-    flow_terms(p, k, ft, ty);
-    s->elbc[k] = (double*)(w + lo.off_elbc[k]);
-    s->ftype[k] = (int8_t*)(w + lo.off_ftype[k]);
-    s->flbc[k] = (double*)(w + lo.off_flbc[k]);
-    s->elbc_used[k] = (p->side[k].el == BP_EL_DIRICHLET || p->side[k].el == BP_EL_TRACTION);
-    if (hipMemcpyAsync(s->elbc[k], et.data(), et.size() * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->flbc[k], ft.data(), ft.size() * 8, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipMemcpyAsync(s->ftype[k], ty.data(), ty.size(), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-      return bail(fail(BP_ERR_DEVICE, "boundary upload failed"));
-  }
-  if (upload_loads(s, p->body_f, p->source_s) != BP_OK) return bail(BP_ERR_DEVICE);
-  if (run_init(s) != BP_OK) return bail(BP_ERR_DEVICE);
-  if (const char* e = std::getenv("BIOT_NO_GRAPH")) s->use_graph = (std::atoi(e) == 0);
-  if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(BP_ERR_DEVICE, "init failed"));
   *out = s;
   return BP_OK;
 }
 
 bp_status bp_destroy(bp_solver* s) {
   if (!s) return BP_OK;
-  if (s->graph) (void)hipGraphExecDestroy(s->graph);
-  if (s->host_pin) (void)hipHostFree(s->host_pin);
+  engine_release(s->E);
   delete s;
   return BP_OK;
 }
 
 bp_status bp_step(bp_solver* s, int32_t nsteps) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
-  if (s->status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
+  if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
   if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
   for (int k = 0; k < nsteps; ++k) {
-    if (s->ne_fixed > 0) {
-      if (s->use_graph && s->stream) {
-        if (!s->graph_valid) BPCHK(build_graph(s));
-        HIPCHK(hipGraphLaunch(s->graph, s->stream));
-      } else {
-        BPCHK(enqueue_fixed_step(s));
-      }
-      s->last_ne = s->ne_fixed;
-      s->total_cycles += s->ne_fixed;
-    } else {
-      bp_status st = adaptive_step(s);
-      if (st != BP_OK) {
-        s->status = st;
-        return st;
-      }
+    bp_status st = s->P.ne_fixed > 0 ? fixed_step(s->E) : adaptive_step(s->E);
+    if (st != BP_OK) {
+      s->P.status = st;
+      return st;
     }
-    s->step += 1;
   }
   return BP_OK;
 }
 
 bp_status bp_set_loads(bp_solver* s, const double* body_f, const double* source_s, int32_t reinit) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
-  HIPCHK(hipStreamSynchronize(s->stream));
-  const bool had_body = s->has_body, had_src = s->has_src;
-  BPCHK(upload_loads(s, body_f, source_s));
-  if (had_body != s->has_body || had_src != s->has_src) s->graph_valid = false;
-  if (reinit) {
-    BPCHK(run_init(s));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    s->step = 0;
-    s->status = BP_OK;
-  }
+  HIPCHK(hipStreamSynchronize(s->E.stream));
+  const bool hb = s->P.has_body, hs = s->P.has_src;
+  BPCHK(upload_loads(s->E.stream, s->P, body_f, source_s));
+  if (hb != s->P.has_body || hs != s->P.has_src) BPCHK(engine_upload(s->E));
+  if (reinit) BPCHK(init_states(s->E));
   return BP_OK;
 }
 
 bp_status bp_get_fields(bp_solver* s, double* eta, double* p, double* sigma, int32_t* step) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
-  BPCHK(run_extract(s));
-  const size_t N = (size_t)s->nx * s->ny;
-  int flag = 0;
-  HIPCHK(hipMemcpyAsync(&flag, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-  if (eta) HIPCHK(hipMemcpyAsync(eta, s->eta, 2 * N * 8, hipMemcpyDeviceToHost, s->stream));
-  if (sigma) HIPCHK(hipMemcpyAsync(sigma, s->sig, 3 * N * 8, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
-  if (p) {
-    BPCHK(download_planes<double>(s, s->pout, s->nx, s->ny, s->lo.pitch, s->lo.plane, p, 1));
-    for (size_t k = 0; k < N; ++k) p[k] /= s->c0;
-  }
-  if (step) *step = s->step;
-  bool finite = true;
-  if (eta)
-    for (size_t k = 0; k < 2 * N && finite; ++k) finite = std::isfinite(eta[k]);
-  if (flag || !finite) {
-    s->status = BP_ERR_DIVERGED;
-    return fail(BP_ERR_DIVERGED, "the solution is not finite");
-  }
-  return BP_OK;
+  BPCHK(extract_fields(s->E));
+  return fields_of(s->E, s->P, eta, p, sigma, step);
 }
 
 bp_status bp_get_state(bp_solver* s, double* f, double* g, double* D1, double* D2, int32_t* step) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
-  const int n = s->step;
-  const int nx = s->nx, ny = s->ny;
+  Prob& P = s->P;
+  hipStream_t st = s->E.stream;
+  const int n = P.step;
+  const int nx = P.nx, ny = P.ny;
   const size_t N = (size_t)nx * ny;
-  const LevelBuf& v = s->lo.lv[s->L];
-  HIPCHK(hipStreamSynchronize(s->stream));
+  const LevelLay& v = P.lo.lv[P.L];
+  HIPCHK(hipStreamSynchronize(st));
   std::vector<double> pr, er;
-  if (s->lo.shift) {
+  if (P.lo.shift) {
     pr.resize(N);
     er.resize(2 * N);
-    BPCHK(down(s, s->lo.fdbl, s->pref, nx, ny, s->lo.pitch, s->lo.plane, pr.data(), 1));
-    BPCHK(down(s, s->lo.fdbl, s->eref, nx, ny, s->lo.pitch, s->lo.plane, er.data(), 2));
+    BPCHK(down(st, P.lo.fdbl, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
+    BPCHK(down(st, P.lo.fdbl, P.d.eref, nx, ny, P.lo.pitch, P.lo.plane, er.data(), 2));
   }
   if (f) {
-    BPCHK(down(s, s->lo.fdbl, s->f[n & 1], nx, ny, s->lo.pitch, s->lo.plane, f, 9));
-    if (s->lo.shift)
+    BPCHK(down(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
+    if (P.lo.shift)
       for (int i = 0; i < 9; ++i)
         for (size_t k = 0; k < N; ++k) f[i * N + k] += W9[i] * pr[k];
   }
   if (g) {
-    BPCHK(down(s, v.dbl, v.gA, nx, ny, v.pitch, v.plane, g, 8));
-    if (s->lo.shift)
+    BPCHK(down(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, g, 8));
+    if (P.lo.shift)
       for (int q = 0; q < 8; ++q)
         for (size_t k = 0; k < N; ++k) g[q * N + k] += geq_host(q, er[k], er[N + k]);
   }
-  if (D1) BPCHK(download_planes<double>(s, s->D[(n + 2) % 3], nx, ny, s->lo.pitch, s->lo.plane, D1, 1));
-  if (D2) BPCHK(download_planes<double>(s, s->D[(n + 1) % 3], nx, ny, s->lo.pitch, s->lo.plane, D2, 1));
-  if (step) *step = s->step;
+  if (D1) BPCHK(download_planes<double>(st, P.d.D[(n + 2) % 3], nx, ny, P.lo.pitch, P.lo.plane, D1, 1));
+  if (D2) BPCHK(download_planes<double>(st, P.d.D[(n + 1) % 3], nx, ny, P.lo.pitch, P.lo.plane, D2, 1));
+  if (step) *step = P.step;
   return BP_OK;
 }
 
@@ -928,86 +988,107 @@ bp_status bp_set_state(bp_solver* s, const double* f, const double* g, const dou
                        int32_t step) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
   if (step < 0) return fail(BP_ERR_ARG, "step < 0");
-  const int nx = s->nx, ny = s->ny;
-  const LevelBuf& v = s->lo.lv[s->L];
-  HIPCHK(hipStreamSynchronize(s->stream));
-  s->step = step;
+  Prob& P = s->P;
+  hipStream_t st = s->E.stream;
+  const int nx = P.nx, ny = P.ny;
+  const LevelLay& v = P.lo.lv[P.L];
+  HIPCHK(hipStreamSynchronize(st));
+  P.step = step;
   const int n = step;
-  // the device phase counter follows the host step count
-  int ph = n;
-  HIPCHK(hipMemcpyAsync(s->phase, &ph, sizeof(int), hipMemcpyHostToDevice, s->stream));
-  if (s->lo.shift) {  // references to zero: stored offsets are the full populations
-    HIPCHK(launch_fill_zero(s->eref, align_up(2 * s->lo.plane * (s->lo.fdbl ? 8 : 4)), s->stream));
-    HIPCHK(launch_fill_zero(s->pref, align_up(s->lo.plane * (s->lo.fdbl ? 8 : 4)), s->stream));
+  int ph[2] = {n, 0};  // phase, flags
+  HIPCHK(hipMemcpyAsync(P.d.phase, ph, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+  if (P.lo.shift) {  // references to zero: stored offsets are the full populations
+    HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+    HIPCHK(launch_fill_zero(P.d.pref, align_up(P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
   }
-  if (f) BPCHK(up(s, s->lo.fdbl, s->f[n & 1], nx, ny, s->lo.pitch, s->lo.plane, f, 9));
-  if (g) BPCHK(up(s, v.dbl, v.gA, nx, ny, v.pitch, v.plane, g, 8));
-  if (D1) BPCHK(upload_planes<double>(s, s->D[(n + 2) % 3], nx, ny, s->lo.pitch, s->lo.plane, D1, 1));
-  if (D2) BPCHK(upload_planes<double>(s, s->D[(n + 1) % 3], nx, ny, s->lo.pitch, s->lo.plane, D2, 1));
-  int zero = 0;
-  HIPCHK(hipMemcpyAsync(s->flags, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(hipStreamSynchronize(s->stream));
-  s->status = BP_OK;
+  if (f) BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
+  if (g) BPCHK(up(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, g, 8));
+  if (D1) BPCHK(upload_planes<double>(st, P.d.D[(n + 2) % 3], nx, ny, P.lo.pitch, P.lo.plane, D1, 1));
+  if (D2) BPCHK(upload_planes<double>(st, P.d.D[(n + 1) % 3], nx, ny, P.lo.pitch, P.lo.plane, D2, 1));
+  HIPCHK(hipStreamSynchronize(st));
+  P.status = BP_OK;
   return BP_OK;
 }
 
 bp_status bp_level_shape(const bp_solver* s, int32_t level, int32_t* nx, int32_t* ny) {
-  if (!s || level < 1 || level > s->L) return fail(BP_ERR_ARG, "bad level");
-  *nx = s->lo.lv[level].nx;
-  *ny = s->lo.lv[level].ny;
+  if (!s || level < 1 || level > s->P.L) return fail(BP_ERR_ARG, "bad level");
+  *nx = s->P.lo.lv[level].nx;
+  *ny = s->P.lo.lv[level].ny;
   return BP_OK;
 }
 
 bp_status bp_apply_elastic(bp_solver* s, int32_t level, const double* g, const double* r, const double* Ft,
                            double* out) {
-  if (!s || level < 1 || level > s->L || !g || !out) return fail(BP_ERR_ARG, "bad arguments");
-  const bool fine = level == s->L;
+  if (!s || level < 1 || level > s->P.L || !g || !out) return fail(BP_ERR_ARG, "bad arguments");
+  Prob& P = s->P;
+  hipStream_t st = s->E.stream;
+  const bool fine = level == P.L;
   if ((fine && r) || (!fine && Ft)) return fail(BP_ERR_ARG, "r applies to coarse levels, Ft to the finest");
-  LevelBuf& v = s->lo.lv[level];
-  if (fine && s->lo.shift)
-    HIPCHK(launch_fill_zero(s->eref, align_up(2 * s->lo.plane * (s->lo.fdbl ? 8 : 4)), s->stream));
-  BPCHK(up(s, v.dbl, v.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
-  if (!fine) BPCHK(up(s, v.dbl, v.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
-  if (fine) BPCHK(up(s, s->lo.fdbl, s->Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));
-  BPCHK(sweep(s, SweepReq{level, kApply, v.gA, v.gB, fine ? nullptr : v.r, fine ? s->Ft : nullptr, nullptr,
-                          nullptr, false, nullptr}));
-  BPCHK(down(s, v.dbl, v.gB, v.nx, v.ny, v.pitch, v.plane, out, 8));
+  const LevelLay& v = P.lo.lv[level];
+  LevelD& D = P.d.lv[level];
+  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+  BPCHK(up(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
+  if (!fine) BPCHK(up(st, v.dbl, D.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
+  if (fine) BPCHK(up(st, P.lo.fdbl, P.d.Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));
+  BPCHK(single_apply(s, level));
+  BPCHK(down(st, v.dbl, D.gB, v.nx, v.ny, v.pitch, v.plane, out, 8));
   return BP_OK;
 }
 
 bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, const double* Ft) {
-  if (!s || level < 1 || level > s->L || !g) return fail(BP_ERR_ARG, "bad arguments");
-  const bool fine = level == s->L;
+  if (!s || level < 1 || level > s->P.L || !g) return fail(BP_ERR_ARG, "bad arguments");
+  Prob& P = s->P;
+  Engine& E = s->E;
+  hipStream_t st = E.stream;
+  const bool fine = level == P.L;
   if ((fine && r) || (!fine && Ft)) return fail(BP_ERR_ARG, "r applies to coarse levels, Ft to the finest");
-  LevelBuf& v = s->lo.lv[level];
-  if (fine && s->lo.shift)
-    HIPCHK(launch_fill_zero(s->eref, align_up(2 * s->lo.plane * (s->lo.fdbl ? 8 : 4)), s->stream));
-  BPCHK(up(s, v.dbl, v.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
-  if (!fine) BPCHK(up(s, v.dbl, v.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
-  if (fine) BPCHK(up(s, s->lo.fdbl, s->Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));
-  BPCHK(vcycle(s, level, false, false, nullptr));
-  BPCHK(down(s, v.dbl, v.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
+  const LevelLay& v = P.lo.lv[level];
+  LevelD& D = P.d.lv[level];
+  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+  BPCHK(up(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
+  if (!fine) BPCHK(up(st, v.dbl, D.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
+  if (fine) BPCHK(up(st, P.lo.fdbl, P.d.Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));
+  // a cycle that starts on level `level` from the given iterate
+  std::vector<Op> ops;
+  const int d = P.L - level;
+  int sel = 0;
+  for (int k = 0; k < E.K; ++k) {
+    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, 0, 0);
+    sel = 1 - sel;
+  }
+  if (level > 1) {
+    add_sweeps(E, ops, d, 1, kRestrict, sel, 0, 0, 0);
+    add_vcycle(E, ops, d + 1, false, false);
+  }
+  for (int k = 0; k < E.K; ++k) {
+    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);
+    sel = 1 - sel;
+  }
+  BPCHK(run_ops(E, ops));
+  BPCHK(down(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
   return BP_OK;
 }
 
 bp_status bp_explicit_force(bp_solver* s, double* Ft) {
   if (!s || !Ft) return fail(BP_ERR_ARG, "bad arguments");
-  int ph = s->step;
-  HIPCHK(hipMemcpyAsync(s->phase, &ph, sizeof(int), hipMemcpyHostToDevice, s->stream));
-  BPCHK(run_force(s));
-  BPCHK(down(s, s->lo.fdbl, s->Ft, s->nx, s->ny, s->lo.pitch, s->lo.plane, Ft, 2));
+  Prob& P = s->P;
+  int ph = P.step;
+  HIPCHK(hipMemcpyAsync(P.d.phase, &ph, sizeof(int), hipMemcpyHostToDevice, s->E.stream));
+  std::vector<Op> ops{cell_op(s->E, OP_FORCE)};
+  BPCHK(run_ops(s->E, ops));
+  BPCHK(down(s->E.stream, P.lo.fdbl, P.d.Ft, P.nx, P.ny, P.lo.pitch, P.lo.plane, Ft, 2));
   return BP_OK;
 }
 
 bp_status bp_stats(const bp_solver* s, bp_run_stats* st) {
   if (!s || !st) return fail(BP_ERR_ARG, "bad arguments");
-  st->step = s->step;
-  st->last_ne = s->last_ne;
-  st->total_cycles = s->total_cycles;
-  st->last_ratio = s->last_ratio;
-  st->levels = s->L;
+  st->step = s->P.step;
+  st->last_ne = s->P.last_ne;
+  st->total_cycles = s->P.total_cycles;
+  st->last_ratio = s->P.last_ratio;
+  st->levels = s->P.L;
   int flag = 0;
-  if (hipMemcpy(&flag, s->flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(&flag, s->P.d.flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(BP_ERR_DEVICE, "stats copy failed");
   st->diverged = flag;
   return BP_OK;
@@ -1015,62 +1096,59 @@ bp_status bp_stats(const bp_solver* s, bp_run_stats* st) {
 
 bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg_us, double* bytes) {
   if (!s || iters < 1 || !avg_us) return fail(BP_ERR_ARG, "bad arguments");
-  LevelBuf& v = s->lo.lv[s->L];
-  const double es = s->lo.fdbl ? 8.0 : 4.0;
-  const double N = (double)s->nx * s->ny;
-  const double shift = s->lo.shift ? 1.0 : 0.0;
-  double b = 0.0;
+  Engine& E = s->E;
+  Prob& P = s->P;
+  const double es = P.lo.fdbl ? 8.0 : 4.0;
+  const double N = (double)P.nx * P.ny;
+  const double shift = P.lo.shift ? 1.0 : 0.0;
+  std::vector<Op> ops;
+  switch (which) {
+    case 0: add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 0); break;
+    case 1:
+      if (P.L < 2) return fail(BP_ERR_ARG, "no coarser level");
+      add_sweeps(E, ops, 0, 1, kRestrict, 0, 0, 0, 0);
+      break;
+    case 2: ops.push_back(flow_op(E)); break;
+    default: ops.push_back(cell_op(E, OP_FORCE)); break;
+  }
+  std::vector<double> psave;
+  if (which == 2) {  // the timed flow launches overwrite the pressure output
+    psave.resize((size_t)P.lo.plane);
+    HIPCHK(hipMemcpyAsync(psave.data(), P.d.pout, P.lo.plane * 8, hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  // keep p_out: the timed flow launches overwrite it
-  std::vector<double> psave;
-  if (which == 2) {
-    psave.resize((size_t)s->lo.plane);
-    HIPCHK(hipMemcpyAsync(psave.data(), s->pout, s->lo.plane * 8, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-  }
-  auto one = [&]() -> bp_status {
-    switch (which) {
-      case 0:
-        return sweep(s, SweepReq{s->L, kSmooth, v.gA, v.gB, nullptr, s->Ft, nullptr, nullptr, false, nullptr});
-      case 1: {
-        if (s->L < 2) return fail(BP_ERR_ARG, "no coarser level");
-        LevelBuf& c = s->lo.lv[s->L - 1];
-        return sweep(s, SweepReq{s->L, kRestrict, v.gA, nullptr, nullptr, s->Ft, nullptr, c.r, false, nullptr});
-      }
-      case 2: return run_flow(s);
-      default: return run_force(s);
-    }
-  };
-  BPCHK(one());  // warm-up
-  HIPCHK(hipEventRecord(e0, s->stream));
-  for (int k = 0; k < iters; ++k) BPCHK(one());
-  HIPCHK(hipEventRecord(e1, s->stream));
+  BPCHK(run_ops(E, ops));  // warm-up
+  HIPCHK(hipEventRecord(e0, E.stream));
+  for (int k = 0; k < iters; ++k) BPCHK(run_ops(E, ops));
+  HIPCHK(hipEventRecord(e1, E.stream));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (which == 2) {
-    HIPCHK(hipMemcpyAsync(s->pout, psave.data(), s->lo.plane * 8, hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpyAsync(P.d.pout, psave.data(), P.lo.plane * 8, hipMemcpyHostToDevice, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
   }
   *avg_us = 1000.0 * ms / iters;
+  double b;
   switch (which) {
     case 0: b = N * (16.0 + 2.0 + 2.0 * shift) * es; break;
     case 1: {
-      const double ce = s->lo.lv[s->L - 1].dbl ? 8.0 : 4.0;
+      const double ce = P.lo.lv[P.L - 1].dbl ? 8.0 : 4.0;
       b = N * (8.0 + 2.0 + 2.0 * shift) * es + (N / 4.0) * 8.0 * ce;
       break;
     }
     case 2:
-      b = N * (18.0 + 8.0 + 2.0 * shift) * es + N * 8.0 * (2.0 + 1.0 + 1.0) + (s->has_src ? N * 8.0 : 0.0) +
-          (s->het ? N * 8.0 : 0.0);
+      b = N * (18.0 + 8.0 + shift) * es + N * 8.0 * (2.0 + 1.0 + 1.0) + (P.has_src ? N * 8.0 : 0.0) +
+          (P.d.omf ? N * 8.0 : 0.0);
       break;
     default:
-      b = N * (9.0 + 2.0) * es + N * 8.0 * 2.0 + (s->has_body ? N * 16.0 : 0.0) + (s->has_src ? N * 8.0 : 0.0) +
-          (s->het ? N * 8.0 : 0.0);
+      b = N * (9.0 + 2.0) * es + N * 8.0 * 2.0 + (P.has_body ? N * 16.0 : 0.0) + (P.has_src ? N * 8.0 : 0.0) +
+          (P.d.omf ? N * 8.0 : 0.0);
       break;
   }
   if (bytes) *bytes = b;
@@ -1080,6 +1158,83 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
 bp_status bp_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   if (!dst || !src || bytes % 16) return fail(BP_ERR_ARG, "bad copy arguments");
   HIPCHK(launch_copy(dst, src, bytes, (hipStream_t)hip_stream));
+  return BP_OK;
+}
+
+// ------------------------------------------------------------------ batch
+bp_status bp_batch_workspace_bytes(const bp_problem* probs, int32_t n, size_t* device_bytes) {
+  if (!probs || n < 1 || !device_bytes) return fail(BP_ERR_ARG, "bad batch arguments");
+  size_t total = 0, te = 0;
+  for (int i = 0; i < n; ++i) {
+    BPCHK(validate(&probs[i]));
+    if (probs[i].prec != probs[0].prec || probs[i].K != probs[0].K || probs[i].ne_fixed != probs[0].ne_fixed)
+      return fail(BP_ERR_ARG, "a batch needs one precision, one K and one fixed V-cycle count");
+    if (probs[i].ne_fixed < 1) return fail(BP_ERR_ARG, "batched problems need a fixed V-cycle count");
+    Layout lo;
+    make_layout(&probs[i], lo);
+    total += lo.total;
+    te += tile_entries_for(lo);
+  }
+  *device_bytes = total + engine_bytes((size_t)n, te);
+  return BP_OK;
+}
+
+bp_status bp_batch_create(const bp_problem* probs, int32_t n, void* device_ws, size_t ws_bytes, void* hip_stream,
+                          bp_batch** out) {
+  if (!out) return fail(BP_ERR_ARG, "null output handle");
+  *out = nullptr;
+  size_t need = 0;
+  BPCHK(bp_batch_workspace_bytes(probs, n, &need));
+  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0 || ws_bytes < need)
+    return fail(BP_ERR_WORKSPACE, "workspace missing, not 256-byte aligned or too small");
+  bp_batch* b = new bp_batch();
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* w = (char*)device_ws;
+  b->P.resize(n);
+  size_t off = 0, te = 0;
+  std::vector<Layout> los(n);
+  for (int i = 0; i < n; ++i) {
+    make_layout(&probs[i], los[i]);
+    te += tile_entries_for(los[i]);
+  }
+  for (int i = 0; i < n; ++i) off += los[i].total;
+  bp_status rc = engine_init(b->E, w + off, need - off, (size_t)n, te, st, los[0].fdbl, los[0].shift, probs[0].K,
+                             probs[0].ne_fixed);
+  off = 0;
+  for (int i = 0; i < n && rc == BP_OK; ++i) {
+    rc = setup_problem(&probs[i], los[i], w + off, st, b->P[i]);
+    off += los[i].total;
+  }
+  if (rc == BP_OK) {
+    for (auto& P : b->P) b->E.probs.push_back(&P);
+    rc = engine_upload(b->E);
+  }
+  if (rc == BP_OK) rc = init_states(b->E);
+  if (rc != BP_OK) {
+    engine_release(b->E);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return BP_OK;
+}
+
+bp_status bp_batch_step(bp_batch* b, int32_t nsteps) {
+  if (!b) return fail(BP_ERR_ARG, "null batch");
+  for (int k = 0; k < nsteps; ++k) BPCHK(fixed_step(b->E));
+  return BP_OK;
+}
+
+bp_status bp_batch_get_fields(bp_batch* b, int32_t i, double* eta, double* p, double* sigma, int32_t* step) {
+  if (!b || i < 0 || i >= (int)b->P.size()) return fail(BP_ERR_ARG, "bad batch index");
+  BPCHK(extract_fields(b->E));
+  return fields_of(b->E, b->P[i], eta, p, sigma, step);
+}
+
+bp_status bp_batch_destroy(bp_batch* b) {
+  if (!b) return BP_OK;
+  engine_release(b->E);
+  delete b;
   return BP_OK;
 }
 

@@ -1,0 +1,103 @@
+// Device descriptors, launch blocks and launcher declarations of the batched
+// Biot LBM engine (gfx950).
+//
+// Every launch works on a list of tiles drawn from one or many problems: a
+// tile entry is (problem index, tile index within the level that the launch
+// addresses).  Levels are aligned from the finest: "depth" d addresses level
+// L_p - d of problem p, so problems with different hierarchy depths share the
+// launches of their common depths (Algorithm 4 recursion aligned top-down).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace biot {
+
+constexpr int kMaxLevels = 16;
+constexpr int kTileY = 12;              // output rows of a sweep tile (even: 2x2 restriction pairs)
+constexpr int kCellBX = 64, kCellBY = 4;  // per-cell kernels: 64 x 4 cells per block
+
+enum SweepMode : int { kSmooth = 0, kRestrict = 1, kApply = 2 };
+
+struct LevelD {
+  void* gA;          // population buffer A (8 planes)
+  void* gB;          // population buffer B
+  void* r;           // coarse right-hand side (8 planes), null on the finest level
+  int nx, ny, pitch;
+  int tiles_x;       // sweep tiles along x: ceil(nx / kTileX)
+  int64_t plane;
+};
+
+// one problem as the kernels see it (device memory, read with scalar loads)
+struct ProbD {
+  LevelD lv[kMaxLevels + 1];  // 1..L, L is the finest
+  int L;
+  int el[4];                  // elastic side types
+  const double* elbc[4];      // finest level: 8 additive terms per boundary cell (or null)
+  const int8_t* ftype[4];     // flow type per boundary cell
+  const double* flbc[4];      // 9 additive terms per boundary cell
+  void* f[2];                 // flow populations, ping-pong by step parity
+  double* D[3];               // D^n rotated by step number mod 3
+  double* pout;               // lattice pressure of the last completed step
+  const double* fbody;        // h^2 c0 f (2 planes) or null
+  const double* src;          // dt s or null
+  const double* omf;          // per-cell flow relaxation rate or null
+  void* Ft;                   // explicit force (2 planes)
+  void* eref;                 // displacement reference (shifted storage) or null
+  void* pref;                 // pressure reference (shifted storage) or null
+  double* eta;                // extraction output (2 dense planes)
+  double* sig;                // extraction output (3 dense planes)
+  double* partials;           // per finest-level tile: sum rho^2, sum g^2
+  double* norm2;              // finalized sums
+  int* phase;                 // completed steps (device copy)
+  int* flags;                 // [0] non-finite seen
+  double om_s, om_d, beta22, kD, cstar, gamma;
+  double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
+  int ntiles_fine;            // sweep tiles of the finest level
+};
+
+struct SweepL {
+  const ProbD* probs;
+  const int2* tiles;
+  int depth;
+  int in_sel;     // 0: buffer A, 1: buffer B, 2: zero input
+  int out_sel;    // 0: A, 1: B
+  int prolong;    // add the coarse correction (coarser level's buffer A) to the input
+  int partials;   // write norm partials (finest level)
+};
+
+struct CellL {    // per-cell kernels over the finest level
+  const ProbD* probs;
+  const int2* tiles;  // (problem, cell block)
+};
+
+struct ProbL {    // one block per problem
+  const ProbD* probs;
+  const int* pids;
+};
+
+template <typename T, typename Tc, int MODE, bool SHIFT>
+hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
+template <typename T, bool SHIFT>
+hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_force(const CellL& a, int ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s);
+template <typename T>
+hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s);
+template <typename T, bool SHIFT>
+hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
+
+hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s);
+hipError_t launch_advance(const ProbL& a, int nprobs, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
+
+inline int sweep_tiles_x(int nx) { return (nx + kTileX - 1) / kTileX; }
+inline int sweep_tiles(int nx, int ny) { return sweep_tiles_x(nx) * ((ny + kTileY - 1) / kTileY); }
+inline int cell_blocks(int nx, int ny) { return ((nx + kCellBX - 1) / kCellBX) * ((ny + kCellBY - 1) / kCellBY); }
+
+}  // namespace biot

@@ -75,6 +75,11 @@ def load_library():
             "bp_time_kernel": [vp, i32, i32, dp, dp],
             "bp_device_copy": [vp, vp, C.c_size_t, vp],
             "bp_destroy": [vp],
+            "bp_batch_workspace_bytes": [C.POINTER(_Problem), i32, C.POINTER(C.c_size_t)],
+            "bp_batch_create": [C.POINTER(_Problem), i32, vp, C.c_size_t, vp, C.POINTER(vp)],
+            "bp_batch_step": [vp, i32],
+            "bp_batch_get_fields": [vp, i32, dp, dp, dp, C.POINTER(i32)],
+            "bp_batch_destroy": [vp],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -256,3 +261,60 @@ def device_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int):
     lib = load_library()
     _check(lib.bp_device_copy(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), nbytes, C.c_void_p(stream_ptr)),
            "bp_device_copy")
+
+
+class Batch:
+    """Many independent problems advanced together (one launch per multigrid
+    depth and phase covers all of them).  Method names follow biotlbm.h."""
+
+    def __init__(self, problems, prec="fp32_shifted", device="cuda:0", stream=None):
+        import torch
+
+        lib = load_library()
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (_Problem * n)()
+        keep = []
+        for i, p in enumerate(self.problems):
+            pb, k = marshal_problem(p, prec)
+            arr[i] = pb
+            keep.append(k)
+        nbytes = C.c_size_t(0)
+        _check(lib.bp_batch_workspace_bytes(arr, n, C.byref(nbytes)), "bp_batch_workspace_bytes")
+        self.ws_bytes = nbytes.value
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p(0)
+        _check(lib.bp_batch_create(arr, n, C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), "bp_batch_create")
+        del keep
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.bp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.problems)
+
+    def step(self, n=1):
+        _check(self._lib.bp_batch_step(self._h, int(n)), "bp_batch_step")
+
+    def fields(self, i):
+        p = self.problems[i]
+        eta = np.zeros((2, p.ny, p.nx))
+        pr = np.zeros((p.ny, p.nx))
+        sig = np.zeros((3, p.ny, p.nx))
+        st = C.c_int32(0)
+        _check(self._lib.bp_batch_get_fields(self._h, int(i), _dptr(eta), _dptr(pr), _dptr(sig), C.byref(st)),
+               "bp_batch_get_fields")
+        return dict(eta=eta, p=pr, sigma=sig, step=st.value)

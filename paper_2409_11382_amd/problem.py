@@ -159,7 +159,7 @@ def terzaghi_paper(alpha: float, n: int, nx=None, **kw) -> Problem:
 # unit load on the central quarter of the top, impermeable under the load and
 # drained elsewhere on the top; the other sides are impermeable rollers.
 # ---------------------------------------------------------------------------
-def loaded_strip(n=512, E=1.0, nu=0.3, kappa=1.0, c0=0.1, alpha=1.0, load=1.0,
+def loaded_strip(n=512, E=1.0, nu=0.3, kappa=1.0, c0=1.0, alpha=1.0, load=1.0,
                  ny=None, dt=None, levels=0, K=4, gamma=0.75, r=0.5, ne_fixed=3,
                  ne_tol=0.0, ne_max=50, whole_top_drained=False) -> Problem:
     nx = n
@@ -277,7 +277,7 @@ class Manufactured:
 def batch_problems(count=256, seed=1, sizes=(64, 128, 256, 512), ne_fixed=3, K=4):
     """Independent loaded-strip problems with square grids drawn uniformly from
     ``sizes``, nu ~ U[0.2, 0.45], alpha ~ U[0.5, 1], log10 kappa ~ U[-2, 0],
-    E = 1, c0 = 0.1, drawn from default_rng(seed)."""
+    E = 1, c0 = 1, drawn from default_rng(seed)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):

@@ -204,8 +204,8 @@ def test_determinism_and_mirror_symmetry(lbm):
     b.step(5)
     A, B = a.fields(), b.fields()
     assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
-    assert np.abs(A["eta"][0] + A["eta"][0][:, ::-1]).max() < 1e-12 * np.abs(A["eta"]).max()
-    assert np.abs(A["p"] - A["p"][:, ::-1]).max() < 1e-12 * np.abs(A["p"]).max()
+    assert np.abs(A["eta"][0] + A["eta"][0][:, ::-1]).max() < 1e-10 * np.abs(A["eta"]).max()
+    assert np.abs(A["p"] - A["p"][:, ::-1]).max() < 1e-10 * np.abs(A["p"]).max()
 
 
 def test_checkpoint_resume_is_bitwise(lbm):
@@ -244,3 +244,26 @@ def test_invalid_problems_rejected(lbm):
     for bad in (dict(c0=0.0), dict(alpha=1.5), dict(gamma=1.0), dict(levels=6)):
         with pytest.raises(lbm.BiotError):
             lbm.Solver(base.replace(**bad))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
+def test_batch_alone_equals_in_mix(lbm, prec):
+    """Problems of different sizes, hierarchy depths, parameters and boundary
+    types advanced together give bitwise the same fields as each alone."""
+    probs = [P.loaded_strip(n=64, alpha=0.7, kappa=0.3, ne_fixed=3),
+             P.loaded_strip(n=128, nu=0.4, alpha=1.0, ne_fixed=3),
+             mixed_walls(124, 68, seed=9).replace(ne_fixed=3, K=4),
+             P.terzaghi(nx=16, ny=64, ne_fixed=3),
+             P.loaded_strip(n=32, ny=96, alpha=0.5, ne_fixed=3)]
+    b = lbm.Batch(probs, prec)
+    b.step(5)
+    for i, p in enumerate(probs):
+        s = lbm.Solver(p, prec)
+        s.step(5)
+        A, B = s.fields(), b.fields(i)
+        _say("batch", i, p.name, rel(B["eta"], A["eta"]))
+        assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"]), (i, p.name)
+        if prec == "fp64":
+            o = Oracle(p, threads=oracle_threads())
+            o.step(5)
+            assert rel(B["eta"], o.fields()["eta"]) < STEP_TOL
