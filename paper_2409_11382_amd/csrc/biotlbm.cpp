@@ -129,8 +129,22 @@ struct Layout {
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
   size_t off_eta, off_sig, off_part, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
   int ntiles_fine = 0;
+  int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
   size_t total = 0;
 };
+
+// the coarse tail covers every level from the largest coarse level whose
+// populations and collision results fit the tail kernel's LDS down to level 1
+int tail_depth_of(const Layout& lo) {
+  if (const char* e = std::getenv("BIOT_NO_TAIL"))
+    if (std::atoi(e) != 0) return 0;
+  for (int l = lo.L - 1; l >= 1; --l) {
+    const LevelLay& v = lo.lv[l];
+    const int cap = v.dbl ? kTailCellsF64 : kTailCellsF32;
+    if (v.nx * v.ny <= cap) return lo.L - l;
+  }
+  return 0;
+}
 
 void make_layout(const bp_problem* p, Layout& lo) {
   lo.L = p->levels > 0 ? p->levels : default_levels(p->nx, p->ny);
@@ -175,6 +189,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.off_eta = take(2 * N * 8);
   lo.off_sig = take(3 * N * 8);
   lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
+  lo.tail_depth = tail_depth_of(lo);
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
   lo.off_scal = take(64);
   for (int s = 0; s < 4; ++s) {
@@ -189,12 +204,12 @@ void make_layout(const bp_problem* p, Layout& lo) {
 // bytes of the engine's own area (descriptors and work lists) for a set of
 // problems
 // entries this problem adds to the engine's tile lists (see engine_upload):
-// every level in the full set, every level but the coarsest in the
-// restriction set, the finest level again for the flow step, and the
+// schedule lists (full and restriction sets) and inspection lists for every
+// level, its tail entry, the finest level again for the flow step, and the
 // finest level's cell blocks
 size_t tile_entries_for(const Layout& lo) {
-  size_t t = 0;
-  for (int l = 1; l <= lo.L; ++l) t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * (l >= 2 ? 2 : 1);
+  size_t t = 1;
+  for (int l = 1; l <= lo.L; ++l) t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny);
   return t;
@@ -392,6 +407,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.lv[l].ny = v.ny;
     d.lv[l].pitch = v.pitch;
     d.lv[l].tiles_x = sweep_tiles_x(v.nx);
+    d.lv[l].dbl = v.dbl ? 1 : 0;
     d.lv[l].plane = v.plane;
   }
   const double lam = p->c0 * p->lambda, mu = p->c0 * p->mu, lm = lam + mu;
@@ -463,7 +479,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
 }
 
 // ---------------------------------------------------------------- engine
-enum OpKind { OP_SWEEP, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
 
 struct Op {
   OpKind kind;
@@ -473,14 +489,19 @@ struct Op {
   SweepL sw{};
   CellL cl{};
   ProbL pl{};
+  TailL tl{};
   int count = 0;          // tiles / problems
 };
 
 // tile-list key of a depth: full set or restriction set, one of three
 // storage groups (level FP32 / coarser FP32, FP32 / FP64, FP64 / FP64)
+// set 0: full set of the time-step schedule (problems not inside their coarse
+// tail at this depth), set 1: its restriction set (problems with a coarser
+// level), sets 2 and 3: the same without the tail (inspection operations)
 struct DepthLists {
-  int off[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  int cnt[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  int off[4][3] = {};
+  int cnt[4][3] = {};
+  int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
 struct Engine {
@@ -523,18 +544,24 @@ bp_status engine_upload(Engine& E) {
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
-    for (int set = 0; set < 2; ++set)
+    for (int set = 0; set < 4; ++set)
       for (int g = 0; g < 3; ++g) {
         E.depth[d].off[set][g] = (int)tiles.size();
         for (size_t i = 0; i < np; ++i) {
           const Prob& P = *E.probs[i];
           const int l = P.L - d;
-          if (l < 1 || (set == 1 && l < 2) || tgroup(E, P, d) != g) continue;
+          const int td = P.lo.tail_depth;
+          if (l < 1 || ((set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
+          if (set < 2 && td > 0 && d >= td) continue;  // inside the problem's coarse tail
           const int nt = sweep_tiles(P.lo.lv[l].nx, P.lo.lv[l].ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
         E.depth[d].cnt[set][g] = (int)tiles.size() - E.depth[d].off[set][g];
       }
+    E.depth[d].tail_off = (int)tiles.size();
+    for (size_t i = 0; i < np; ++i)
+      if (E.probs[i]->lo.tail_depth == d && d > 0) tiles.push_back(make_int2((int)i, 0));
+    E.depth[d].tail_cnt = (int)tiles.size() - E.depth[d].tail_off;
   }
   E.fine_off = (int)tiles.size();
   for (size_t i = 0; i < np; ++i) {
@@ -590,22 +617,39 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
 // Algorithm 4 at depth d for every problem that has a level there.  The
 // iterate of a level starts in buffer A (zero at coarse depths) and ends in A
 // after its 2K smoothing sweeps.  first_done: the first pre-smoothing sweep
-// was already issued (adaptive mode).
-void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last) {
+// was already issued (adaptive mode).  tail: problems whose coarse tail starts
+// at this depth run it in one launch (time-step schedule); without it every
+// level is swept by the tile kernels (inspection operations).
+void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true) {
+  if (d >= E.maxL) return;
+  const int full = tail ? 0 : 2, restr = full + 1;
+  if (tail && E.depth[d].tail_cnt > 0) {
+    Op o;
+    o.kind = OP_TAIL;
+    o.tl.probs = E.d_probs;
+    o.tl.pids = (const int*)(E.d_tiles + E.depth[d].tail_off);
+    o.tl.depth = d;
+    o.tl.K = E.K;
+    o.count = E.depth[d].tail_cnt;
+    ops.push_back(o);
+  }
+  bool here = false;
+  for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
+  if (!here) return;
   int sel = 0;
   for (int k = 0; k < E.K; ++k) {
-    if (!(k == 0 && first_done)) add_sweeps(E, ops, d, 0, kSmooth, (d > 0 && k == 0) ? 2 : sel, 1 - sel, 0, 0);
+    if (!(k == 0 && first_done)) add_sweeps(E, ops, d, full, kSmooth, (d > 0 && k == 0) ? 2 : sel, 1 - sel, 0, 0);
     sel = 1 - sel;
   }
   bool deeper = false;
-  for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[1][g] > 0;
+  for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   if (deeper) {
-    add_sweeps(E, ops, d, 1, kRestrict, sel, 0, 0, 0);
-    add_vcycle(E, ops, d + 1, false, false);
+    add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
+    add_vcycle(E, ops, d + 1, false, false, tail);
   }
   for (int k = 0; k < E.K; ++k) {
     const int part = (partials_last && d == 0 && k == E.K - 1) ? 1 : 0;
-    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, part);
+    add_sweeps(E, ops, d, full, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, part);
     sel = 1 - sel;
   }
 }
@@ -678,6 +722,7 @@ hipError_t run_op(const Engine& E, const Op& o) {
     case OP_EXTRACT:
       if (E.fdbl) return E.shift ? launch_extract<double, true>(o.cl, o.count, s) : launch_extract<double, false>(o.cl, o.count, s);
       return E.shift ? launch_extract<float, true>(o.cl, o.count, s) : launch_extract<float, false>(o.cl, o.count, s);
+    case OP_TAIL: return launch_tail(o.tl, o.count, s);
     case OP_FINALIZE: return launch_finalize(o.pl, o.count, s);
     case OP_ADVANCE: return launch_advance(o.pl, o.count, s);
   }
@@ -740,6 +785,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
 }
 
 void engine_release(Engine& E) {
+  (void)hipStreamSynchronize(E.stream);  // queued work may still read the pinned staging buffer
   if (E.graph) (void)hipGraphExecDestroy(E.graph);
   E.graph = nullptr;
   if (E.host_pin) (void)hipHostFree(E.host_pin);
@@ -864,7 +910,7 @@ namespace {
 // one application on one level of a single-problem engine: buffer A -> B
 bp_status single_apply(bp_solver* s, int level) {
   std::vector<Op> ops;
-  add_sweeps(s->E, ops, s->P.L - level, 0, kApply, 0, 1, 0, 0);
+  add_sweeps(s->E, ops, s->P.L - level, 2, kApply, 0, 1, 0, 0);
   return run_ops(s->E, ops);
 }
 
@@ -1051,18 +1097,27 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
   // a cycle that starts on level `level` from the given iterate
   std::vector<Op> ops;
   const int d = P.L - level;
-  int sel = 0;
-  for (int k = 0; k < E.K; ++k) {
-    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, 0, 0);
-    sel = 1 - sel;
-  }
-  if (level > 1) {
-    add_sweeps(E, ops, d, 1, kRestrict, sel, 0, 0, 0);
-    add_vcycle(E, ops, d + 1, false, false);
-  }
-  for (int k = 0; k < E.K; ++k) {
-    add_sweeps(E, ops, d, 0, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);
-    sel = 1 - sel;
+  // a zero iterate on the coarse tail's top level is what the time-step
+  // schedule hands to the tail kernel: run that; any other cycle runs on the
+  // tile kernels
+  bool zero = !fine;
+  for (size_t k = 0; k < (size_t)8 * v.nx * v.ny && zero; ++k) zero = g[k] == 0.0;
+  if (zero && d == P.lo.tail_depth) {
+    add_vcycle(E, ops, d, false, false, true);
+  } else {
+    int sel = 0;
+    for (int k = 0; k < E.K; ++k) {
+      add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, 0, 0);
+      sel = 1 - sel;
+    }
+    if (level > 1) {
+      add_sweeps(E, ops, d, 3, kRestrict, sel, 0, 0, 0);
+      add_vcycle(E, ops, d + 1, false, false, false);
+    }
+    for (int k = 0; k < E.K; ++k) {
+      add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);
+      sel = 1 - sel;
+    }
   }
   BPCHK(run_ops(E, ops));
   BPCHK(down(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
@@ -1117,18 +1172,37 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
     HIPCHK(hipMemcpyAsync(psave.data(), P.d.pout, P.lo.plane * 8, hipMemcpyDeviceToHost, E.stream));
     HIPCHK(hipStreamSynchronize(E.stream));
   }
+  // the launches are captured into one graph so that the events see device
+  // time, not the host's launch rate
+  BPCHK(run_ops(E, ops));  // warm-up
+  HIPCHK(hipStreamSynchronize(E.stream));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHK(hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal));
+  bp_status cap = BP_OK;
+  for (int k = 0; k < iters && cap == BP_OK; ++k) cap = run_ops(E, ops);
+  hipError_t ce = hipStreamEndCapture(E.stream, &graph);
+  if (cap != BP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return cap;
+  }
+  HIPCHK(ce);
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(ie);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  BPCHK(run_ops(E, ops));  // warm-up
+  HIPCHK(hipGraphLaunch(exec, E.stream));  // warm-up of the graph
   HIPCHK(hipEventRecord(e0, E.stream));
-  for (int k = 0; k < iters; ++k) BPCHK(run_ops(E, ops));
+  HIPCHK(hipGraphLaunch(exec, E.stream));
   HIPCHK(hipEventRecord(e1, E.stream));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(exec);
   if (which == 2) {
     HIPCHK(hipMemcpyAsync(P.d.pout, psave.data(), P.lo.plane * 8, hipMemcpyHostToDevice, E.stream));
     HIPCHK(hipStreamSynchronize(E.stream));

@@ -27,6 +27,7 @@ struct LevelD {
   void* r;           // coarse right-hand side (8 planes), null on the finest level
   int nx, ny, pitch;
   int tiles_x;       // sweep tiles along x: ceil(nx / kTileX)
+  int dbl;           // FP64 storage
   int64_t plane;
 };
 
@@ -78,6 +79,22 @@ struct ProbL {    // one block per problem
   const int* pids;
 };
 
+// Coarse "tail" of the multigrid recursion: one 1024-thread workgroup per
+// problem runs Algorithm 4 for every level from L - depth down to 1, with the
+// level's collision results in LDS and only workgroup barriers between sweeps.
+// One cell per thread: a level of more cells keeps one CU's SIMDs busy for
+// longer than the tile kernels take to sweep it across many CUs.
+constexpr int kTailThreads = 1024;
+constexpr int kTailCellsF32 = 1024;   // largest tail level (cells) in FP32 storage
+constexpr int kTailCellsF64 = 1024;   // and in FP64 storage
+constexpr int kTailLdsBytes = 9 * kTailCellsF64 * 8;
+struct TailL {
+  const ProbD* probs;
+  const int* pids;
+  int depth;       // depth of the tail's top level
+  int K;           // smoothing steps
+};
+
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
@@ -91,6 +108,7 @@ hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
 
+hipError_t launch_tail(const TailL& a, int nprobs, hipStream_t s);
 hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_advance(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

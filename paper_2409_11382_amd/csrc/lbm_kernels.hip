@@ -669,6 +669,266 @@ hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s) {
 }
 
 // ======================================================================
+// coarse tail of the multigrid recursion: one workgroup per problem runs
+// Algorithm 4 on all levels from L - depth down to the coarsest.  Every cell
+// of a level is owned by one thread (at most 4 per thread), which keeps the
+// level's iterate and right-hand side in registers across its sweeps; D(g)
+// and the post-collision populations live in LDS.  Global memory (L2-resident
+// at these sizes) is touched only between levels: right-hand sides going
+// down, iterates kept for the ascent and the coarse correction coming up.
+// Coarse levels carry homogeneous boundary data and no explicit force.
+// ======================================================================
+// population q arriving at (x, y); sG holds post-collision populations of the
+// level, q-major and dense: sG[q * n + y * nx + x]
+template <typename T>
+__device__ __forceinline__ T tail_pull(const int q, int x, int y, int nx, int ny, const int* el, const T* sG,
+                                       int n) {
+  const int cx = cx8(q), cy = cy8(q);
+  int sx = x - cx, sy = y - cy;
+  const bool perx = el[kLeft] == kElPeriodic, pery = el[kBottom] == kElPeriodic;
+  bool ox = sx < 0 || sx >= nx, oy = sy < 0 || sy >= ny;
+  if (ox && perx) {
+    sx = (sx + nx) % nx;
+    ox = false;
+  }
+  if (oy && pery) {
+    sy = (sy + ny) % ny;
+    oy = false;
+  }
+  if (!ox && !oy) return sG[q * n + sy * nx + sx];
+  const int elx = cx > 0 ? el[kLeft] : el[kRight];
+  const int ely = cy > 0 ? el[kBottom] : el[kTop];
+  bool usex;
+  if (ox && oy) {
+    if (elx == kElSymmetry && ely == kElSymmetry) return sG[opp8(q) * n + y * nx + x];
+    usex = ely == kElSymmetry;
+  } else if (ox) {
+    if (elx == kElSymmetry) return sG[mx8(q) * n + sy * nx + x];
+    usex = true;
+  } else {
+    if (ely == kElSymmetry) return sG[my8(q) * n + y * nx + sx];
+    usex = false;
+  }
+  const T o = sG[opp8(q) * n + y * nx + x];
+  return (usex ? elx : ely) == kElDirichlet ? o : -o;  // homogeneous bounce-back rules
+}
+
+template <typename T>
+__device__ __forceinline__ ElConst<T> tail_consts(const ProbD& P) {
+  ElConst<T> k;
+  k.om_s = T(P.om_s);
+  k.om_d = T(P.om_d);
+  k.beta22 = T(P.beta22);
+  k.kD = T(P.kD);
+  k.cstar = T(P.cstar);
+  k.gamma = T(P.gamma);
+  return k;
+}
+
+// one application of S on a whole level held by the workgroup: thread t owns
+// cells t, t + 1024, ...; G (iterate) and R (right-hand side) in registers.
+// blend: G <- (1 - gamma) G + gamma S(G); otherwise G <- G - S(G) (residual).
+// Two barriers; sD and sG may be reused right after the return.
+template <typename T, int NC>
+__device__ __forceinline__ void tail_relax(const ProbD& P, const ElConst<T>& k, int nx, int ny, T (&G)[NC][8],
+                                           const T (&R)[NC][8], T* sD, T* sG, bool blend) {
+  const int n = nx * ny, t = threadIdx.x;
+  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = t + kTailThreads * c4;
+    if (c < n) sD[c] = k.kD * el_ms(G[c4]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = t + kTailThreads * c4;
+    if (c >= n) continue;
+    const int x = c % nx, y = c / nx;
+    T v[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx)
+        v[dy + 1][dx + 1] = sD[ghost_map(y + dy, ny, pery) * nx + ghost_map(x + dx, nx, perx)];
+    T gx_, gy_;
+    grad_c(v, gx_, gy_);
+    T u[8], s8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = G[c4][q] - R[c4][q];
+    el_collide(u, k.cstar * gx_, k.cstar * gy_, k, s8);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = s8[q];
+  }
+  __syncthreads();
+  const T gam = k.gamma, omg = T(1) - k.gamma;
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = t + kTailThreads * c4;
+    if (c >= n) continue;
+    const int x = c % nx, y = c / nx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const T gi = tail_pull<T>(q, x, y, nx, ny, P.el, sG, n);
+      G[c4][q] = blend ? omg * G[c4][q] + gam * gi : G[c4][q] - gi;
+    }
+  }
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void tail_load(const LevelD& V, const void* buf, T (&A)[NC][8]) {
+  const int n = V.nx * V.ny;
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = threadIdx.x + kTailThreads * c4;
+    const int64_t idx = c < n ? (int64_t)(c / V.nx) * V.pitch + c % V.nx : 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) A[c4][q] = c < n ? ((const T*)buf)[q * V.plane + idx] : T(0);
+  }
+}
+
+template <typename T, int NC>
+__device__ __forceinline__ void tail_store(const LevelD& V, void* buf, const T (&A)[NC][8]) {
+  const int n = V.nx * V.ny;
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = threadIdx.x + kTailThreads * c4;
+    if (c >= n) continue;
+    const int64_t idx = (int64_t)(c / V.nx) * V.pitch + c % V.nx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ((T*)buf)[q * V.plane + idx] = A[c4][q];
+  }
+}
+
+// descent on level l: K pre-smoothing sweeps from zero, iterate to buffer A,
+// restricted residual (2 x 2 sums) to the right-hand side of level l - 1
+template <typename T, typename Tc>
+__device__ __forceinline__ void tail_descend(const ProbD& P, int l, int K, char* lds) {
+  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
+  const LevelD& V = P.lv[l];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  T G[NC][8], R[NC][8];
+  tail_load<T, NC>(V, V.r, R);
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
+  for (int s = 0; s < K; ++s) tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, true);
+  tail_store<T, NC>(V, V.gA, G);
+  tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, false);
+  __syncthreads();  // every pull has read sG
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = threadIdx.x + kTailThreads * c4;
+    if (c >= n) continue;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[c4][q];
+  }
+  __syncthreads();
+  const LevelD& C = P.lv[l - 1];
+  const int cnx = nx / 2, cn = cnx * (ny / 2);
+  Tc* rc = (Tc*)C.r;
+  for (int c = threadIdx.x; c < cn; c += kTailThreads) {
+    const int X = c % cnx, Y = c / cnx;
+    const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      rc[q * C.plane + (int64_t)Y * C.pitch + X] =
+          Tc((sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]));
+  }
+  __syncthreads();  // the right-hand side is complete before level l - 1 reads it
+}
+
+// coarsest level: 2K smoothing sweeps from zero, iterate to buffer A
+template <typename T>
+__device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, char* lds) {
+  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
+  const LevelD& V = P.lv[1];
+  T* sD = (T*)lds;
+  T* sG = sD + V.nx * V.ny;
+  const ElConst<T> k = tail_consts<T>(P);
+  T G[NC][8], R[NC][8];
+  tail_load<T, NC>(V, V.r, R);
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
+  for (int s = 0; s < 2 * K; ++s) tail_relax<T, NC>(P, k, V.nx, V.ny, G, R, sD, sG, true);
+  tail_store<T, NC>(V, V.gA, G);
+  __syncthreads();
+}
+
+// ascent on level l: iterate plus injected coarse correction, K
+// post-smoothing sweeps, iterate to buffer A
+template <typename T, typename Tc>
+__device__ __forceinline__ void tail_ascend(const ProbD& P, int l, int K, char* lds) {
+  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
+  const LevelD& V = P.lv[l];
+  const LevelD& C = P.lv[l - 1];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  T G[NC][8], R[NC][8];
+  tail_load<T, NC>(V, V.r, R);
+  tail_load<T, NC>(V, V.gA, G);
+  const Tc* ec = (const Tc*)C.gA;
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = threadIdx.x + kTailThreads * c4;
+    if (c >= n) continue;
+    const int64_t cidx = (int64_t)((c / nx) >> 1) * C.pitch + ((c % nx) >> 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[c4][q] += T(ec[q * C.plane + cidx]);
+  }
+  for (int s = 0; s < K; ++s) tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, true);
+  tail_store<T, NC>(V, V.gA, G);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
+  extern __shared__ char lds[];
+  const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
+  const int lt = P.L - a.depth;
+  for (int l = lt; l >= 2; --l) {
+    if (P.lv[l].dbl)
+      tail_descend<double, double>(P, l, a.K, lds);
+    else if (P.lv[l - 1].dbl)
+      tail_descend<float, double>(P, l, a.K, lds);
+    else
+      tail_descend<float, float>(P, l, a.K, lds);
+  }
+  if (P.lv[1].dbl)
+    tail_coarsest<double>(P, a.K, lds);
+  else
+    tail_coarsest<float>(P, a.K, lds);
+  for (int l = 2; l <= lt; ++l) {
+    if (P.lv[l].dbl)
+      tail_ascend<double, double>(P, l, a.K, lds);
+    else if (P.lv[l - 1].dbl)
+      tail_ascend<float, double>(P, l, a.K, lds);
+    else
+      tail_ascend<float, float>(P, l, a.K, lds);
+  }
+}
+
+hipError_t launch_tail(const TailL& a, int nprobs, hipStream_t s) {
+  if (nprobs <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       kTailLdsBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_tail, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  return hipGetLastError();
+}
+
+// ======================================================================
 // per-problem kernels
 // ======================================================================
 // fixed-order FP64 sum of the finest level's norm partials

@@ -167,7 +167,10 @@ class Solver:
         _check(lib.bp_workspace_bytes(C.byref(pb), C.byref(n)), "bp_workspace_bytes")
         self.ws_bytes = n.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the library replays each time
+        # step as one captured HIP graph, which the legacy null stream cannot hold
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.ws.record_stream(self.stream)
         h = C.c_void_p(0)
         _check(lib.bp_create(C.byref(pb), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                              C.c_void_p(self.stream.cuda_stream), C.byref(h)), "bp_create")
@@ -284,7 +287,10 @@ class Batch:
         self.ws_bytes = nbytes.value
         self.device = torch.device(device)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): the library replays each time
+        # step as one captured HIP graph, which the legacy null stream cannot hold
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.ws.record_stream(self.stream)
         h = C.c_void_p(0)
         _check(lib.bp_batch_create(arr, n, C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)), "bp_batch_create")

@@ -43,3 +43,16 @@ def problems_small():
     f, s = M.loads(0.2)
     out["periodic_64"] = M.problem.replace(body_f=f, source_s=s)
     return out
+
+
+def tail_level(shapes, prec):
+    """Top level of the multigrid tail that one workgroup runs (0: none): the
+    largest coarse level whose cells fit the tail kernel (1024, one cell
+    per thread).
+    shapes[l - 1] is the (nx, ny) of level l."""
+    L = len(shapes)
+    for l in range(L - 1, 0, -1):
+        nx, ny = shapes[l - 1]
+        if nx * ny <= 1024:
+            return l
+    return 0

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from conftest import oracle_threads
-from gpu_helpers import mixed_walls, problems_small, rel
+from gpu_helpers import mixed_walls, problems_small, rel, tail_level
 from oracle.oracle import Oracle
 from paper_2409_11382_amd import problem as P
 
@@ -83,6 +83,29 @@ def test_vcycle_and_force(lbm, name):
     err = np.abs(ga - gb).max() / np.abs(gb).max()
     _say("  vcycle max rel", err)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["terzaghi_8x128", "mixed_124x68", "periodic_64"])
+def test_tail_cycle(lbm, name, prec):
+    """The coarse levels that one workgroup runs per problem: a V-cycle from a
+    zero iterate on the tail's top level against the oracle's cycle."""
+    p = problems_small()[name]
+    s = lbm.Solver(p, prec)
+    o = Oracle(p, threads=oracle_threads())
+    shapes = [s.level_shape(l) for l in range(1, o.levels + 1)]
+    lt = tail_level(shapes, prec)
+    _say("tail", name, prec, "top level", lt, shapes[lt - 1] if lt else None)
+    assert lt >= 1
+    nx, ny = shapes[lt - 1]
+    rng = np.random.default_rng(23)
+    r = rng.standard_normal((8, ny, nx)) * 0.1
+    g0 = np.zeros((8, ny, nx))
+    ga = s.mg_cycle(lt, g0.copy(), r, None)
+    gb = o.mg_cycle(lt, g0.copy(), r, None)
+    err = np.abs(ga - gb).max() / np.abs(gb).max()
+    _say("  tail cycle max rel", err)
+    assert err < (1e-12 if prec == "fp64" else 2e-5)
 
 
 def _compare_steps(lbm, p, nsteps, prec="fp64", loads=None, tol=STEP_TOL, check_every=None):
