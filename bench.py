@@ -1,18 +1,26 @@
 """Benchmark: coupled-step MLUPS of the Biot LBM on one MI355X.
 
-Workload: the 2D loaded-strip consolidation problem on 512 x 512 cells (unit load
-on the central quarter of the top, drained elsewhere on the top, impermeable
-rollers on the other sides; E = 1, nu = 0.3, kappa = 1, c0 = 1, alpha = 1;
-multigrid with 9 levels, K = 4, gamma = 3/4, 3 V-cycles per step, centred
-coupling r = 1/2).  A step is one full coupled time step (explicit force, three
-V-cycles, flow update) over the whole grid; inputs are resident in HBM.
+Workload (``value``): the 2D loaded-strip consolidation problem on 512 x 512
+cells (unit load on the central quarter of the top, drained elsewhere on the
+top, impermeable rollers on the other sides; E = 1, nu = 0.3, kappa = 1,
+c0 = 1, alpha = 1; multigrid with 9 levels, K = 4, gamma = 3/4, 3 V-cycles per
+step, centred coupling r = 1/2) in FP32 with shifted populations.  A step is
+one full coupled time step (explicit force, three V-cycles, flow update) over
+the whole grid; inputs are resident in HBM when the timed region starts.
 
-Prints one JSON line.  ``value`` is FP32 (shifted storage) MLUPS; the FP64
-path is reported beside it.
+Beside it: the FP64 path on the same workload and its agreement with the FP32
+result, alpha = 1/2, the batched workload (256 loaded-strip problems of mixed
+size and parameters advanced together), the heterogeneous 2048 x 2048 strip,
+the roofline of the dominant kernel and the FP64 oracle on the host cores.
+
+Prints one JSON line.  ``--kernel-only`` runs just the dominant kernel's timed
+launches and a plain device copy of known size (the command that the hardware
+counter profiles are taken from).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,11 +31,59 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_device.h", "lbm_engine.h")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fine_sweep_fp32_shifted_512.txt")
+COPY_BYTES = 256 << 20
 
 
 def _rel(a, b):
     import numpy as np
     return float(np.sqrt(np.sum((a - b) ** 2)) / np.sqrt(np.sum(b * b)))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2409_11382_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or
+    None when the summary is missing or the kernel sources changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def step_bytes_per_cell(p, fp64: bool, shifted: bool):
+    """Algorithmic bytes per fine cell and coupled step (each value a step must
+    read or write, once), from the level hierarchy actually in use."""
+    s = 8.0 if fp64 else 4.0
+    K, ne = p.K, p.ne_fixed
+    fine = 2 * K * (8 + 8 + 2) + (8 + 2 + 2) + 2     # sweeps, residual + restriction, prolongation
+    if shifted:
+        fine += 2 * K * 2                            # displacement reference read by each sweep
+    coarse = (2 * K * (8 + 8 + 8) + 20) / 3.0        # all coarse levels, per fine cell
+    per_cycle = (fine + coarse) * s
+    force = (9 + 2) * s + 2 * 8
+    flow = 18 * s + 3 * 8
+    extract = 8
+    rebase = (17 + 3) * s if shifted else 0.0
+    return ne * per_cycle + force + flow + extract + rebase
 
 
 def time_steps(solver, steps, warmup):
@@ -59,9 +115,78 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    return {"value": problem.ncells * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} coupled steps of the same 512x512 workload after 1 untimed step, FP64 C oracle, "
-                      f"{threads} OpenMP threads"}
+    return {"value": round(problem.ncells * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} coupled steps of the same {problem.nx}x{problem.ny} workload after 1 untimed step, "
+                      f"FP64 C oracle, {threads} OpenMP threads"}
+
+
+def dominant_kernel(solver, iters):
+    """The finest-level smoothing sweep: average device time of `iters`
+    back-to-back launches (one captured graph, HIP events on the solver's
+    stream) and its algorithmic bytes per launch."""
+    us, nbytes = solver.time_kernel(0, iters)
+    achieved = nbytes / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_tsweep<float,float,smooth,shift> (finest-level smoothing sweep)",
+            "avg_us": round(us, 3), "bytes_per_launch": nbytes,
+            "bytes_per_cell": 80, "launches_timed": iters}
+
+
+def batched(steps, warmup, count=256):
+    """256 independent loaded-strip problems (grids 64..512, random material
+    parameters) advanced together in FP32 with shifted populations."""
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    probs = P.batch_problems(count=count, seed=1)
+    cells = sum(p.ncells for p in probs)
+    b = lbm.Batch(probs, "fp32_shifted")
+    wall, _ = time_steps(b, steps, warmup)
+    per_step = wall / steps
+    out = {"problems": count, "cells": cells, "steps_timed": steps,
+           "mlups": round(cells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * per_step, 4),
+           "solves_per_s_300_steps": round(count / (300 * per_step), 3)}
+    b.close()
+    return out
+
+
+def heterogeneous(steps, warmup, n=2048):
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    p = P.heterogeneous_strip(n=n, ne_fixed=3, K=4)
+    res = {}
+    fields = {}
+    for prec in ("fp32_shifted", "fp64"):
+        s = lbm.Solver(p, prec)
+        wall, _ = time_steps(s, steps, warmup)
+        res[prec] = {"mlups": round(p.ncells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * wall / steps, 4)}
+        fields[prec] = s.fields()
+        s.close()
+    res["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(fields["fp32_shifted"][k], fields["fp64"][k])
+                                             for k in ("eta", "p")}
+    res["steps"] = steps + warmup
+    return res
+
+
+def kernel_only(iters):
+    """Dominant kernel launches and a plain copy of COPY_BYTES bytes, for the
+    kernel-trace and hardware-counter profiles."""
+    import torch
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    prob = P.loaded_strip(n=512, alpha=1.0, ne_fixed=3, K=4)
+    s = lbm.Solver(prob, "fp32_shifted")
+    s.step(2)
+    rl = dominant_kernel(s, iters)
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        lbm.device_copy(dst.data_ptr(), src.data_ptr(), COPY_BYTES, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": rl, "copy_bytes": COPY_BYTES, "kernel_source_sha256_16": kernel_source_hash()}),
+          flush=True)
 
 
 def main():
@@ -71,12 +196,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run")
-    ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--no-extra", action="store_true", help="only the headline workload and its FP64 twin")
+    ap.add_argument("--batch-steps", type=int, default=30)
+    ap.add_argument("--het-steps", type=int, default=100)
+    ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--kernel-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(problems shard one per GPU; see DESIGN.md)", file=sys.stderr)
+              "(independent problems shard one per GPU, a single grid by 2D domain decomposition; "
+              "neither is built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -85,16 +214,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lbm.load_library()
+    if args.kernel_only:
+        kernel_only(args.kernel_iters)
+        return
     prob = P.loaded_strip(n=args.n, alpha=1.0, ne_fixed=3, K=4)
     N = prob.ncells
 
     s32 = lbm.Solver(prob, "fp32_shifted")
     wall32, ev32 = time_steps(s32, args.steps, args.warmup)
     mlups32 = N * args.steps / wall32 / 1e6
-    # dominant kernel: the finest-level smoothing sweep (HIP events on the solver stream)
-    us, nbytes = s32.time_kernel(0, args.kernel_iters)
-    achieved = nbytes / (us * 1e-6) / 1e9
+    roof = dominant_kernel(s32, args.kernel_iters)
+    roof["traffic"] = measured_traffic()
     F32 = s32.fields()
+    s32.close()
+    b_step = step_bytes_per_cell(prob, fp64=False, shifted=True)
 
     out = {
         "metric": "coupled-step MLUPS (FP32 vs FP64) + batched solves/s and p99 latency",
@@ -112,21 +245,28 @@ def main():
         "config": {"workload": f"loaded_strip_{args.n}x{args.n}", "alpha": prob.alpha, "nu": 0.3, "E": 1.0,
                    "kappa": float(prob.kappa), "c0": prob.c0, "levels": prob.num_levels(), "K": prob.K,
                    "gamma": prob.gamma, "ne_fixed": prob.ne_fixed, "r": prob.r,
-                   "precision": "fp32_shifted (fp64 D, coupling, norms, coarsest)"},
-        "roofline": {"bound": "hbm", "kernel": "finest-level smoothing sweep (k_tsweep<float,float,smooth,shift>)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_us": round(us, 3), "bytes_per_launch": nbytes},
+                   "precision": "fp32_shifted (fp64 D, coupling, norms, coarsest level)"},
+        "roofline": roof,
+        "step_roofline": {"bytes_per_cell_step": round(b_step, 1),
+                          "achieved_GBs": round(mlups32 * 1e6 * b_step / 1e9, 1),
+                          "frac": round(mlups32 * 1e6 * b_step / (HBM_PEAK_GBS * 1e9), 4)},
         "event_ms_per_step": round(1e3 * ev32 / args.steps, 5),
     }
-    if not args.no_fp64:
-        s64 = lbm.Solver(prob, "fp64")
-        wall64, _ = time_steps(s64, args.steps, args.warmup)
-        F64 = s64.fields()
-        out["fp64"] = {"value": round(N * args.steps / wall64 / 1e6, 3), "unit": "MLUPS",
-                       "ms_per_step": round(1e3 * wall64 / args.steps, 5)}
-        out["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(F32[k], F64[k]) for k in ("eta", "p")}
-        out["fp32_speedup_over_fp64"] = round(wall64 / wall32, 3)
+    s64 = lbm.Solver(prob, "fp64")
+    wall64, _ = time_steps(s64, args.steps, args.warmup)
+    F64 = s64.fields()
+    s64.close()
+    out["fp64"] = {"value": round(N * args.steps / wall64 / 1e6, 3), "unit": "MLUPS",
+                   "ms_per_step": round(1e3 * wall64 / args.steps, 5)}
+    out["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(F32[k], F64[k]) for k in ("eta", "p")}
+    out["fp32_speedup_over_fp64"] = round(wall64 / wall32, 3)
+    if not args.no_extra:
+        s05 = lbm.Solver(P.loaded_strip(n=args.n, alpha=0.5, ne_fixed=3, K=4), "fp32_shifted")
+        w05, _ = time_steps(s05, args.steps // 5, 2)
+        s05.close()
+        out["alpha_0.5"] = {"value": round(N * (args.steps // 5) / w05 / 1e6, 3), "unit": "MLUPS"}
+        out["batched"] = batched(args.batch_steps, 2)
+        out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -678,11 +678,12 @@ hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s) {
 // down, iterates kept for the ascent and the coarse correction coming up.
 // Coarse levels carry homogeneous boundary data and no explicit force.
 // ======================================================================
-// population q arriving at (x, y); sG holds post-collision populations of the
-// level, q-major and dense: sG[q * n + y * nx + x]
-template <typename T>
-__device__ __forceinline__ T tail_pull(const int q, int x, int y, int nx, int ny, const int* el, const T* sG,
-                                       int n) {
+// Every homogeneous rule of a coarse level gives the population q arriving at
+// (x, y) as plus or minus one post-collision value of the level: interior and
+// periodic pulls, mirror images at symmetry walls, bounce-back (Dirichlet) and
+// anti-bounce-back (traction).  The code returned is that value's index in sG
+// (q-major, dense: q * n + y * nx + x) with bit 15 set for a minus sign.
+__device__ __forceinline__ uint32_t tail_pull_code(const int q, int x, int y, int nx, int ny, const int* el, int n) {
   const int cx = cx8(q), cy = cy8(q);
   int sx = x - cx, sy = y - cy;
   const bool perx = el[kLeft] == kElPeriodic, pery = el[kBottom] == kElPeriodic;
@@ -695,23 +696,52 @@ __device__ __forceinline__ T tail_pull(const int q, int x, int y, int nx, int ny
     sy = (sy + ny) % ny;
     oy = false;
   }
-  if (!ox && !oy) return sG[q * n + sy * nx + sx];
+  if (!ox && !oy) return (uint32_t)(q * n + sy * nx + sx);
   const int elx = cx > 0 ? el[kLeft] : el[kRight];
   const int ely = cy > 0 ? el[kBottom] : el[kTop];
   bool usex;
   if (ox && oy) {
-    if (elx == kElSymmetry && ely == kElSymmetry) return sG[opp8(q) * n + y * nx + x];
+    if (elx == kElSymmetry && ely == kElSymmetry) return (uint32_t)(opp8(q) * n + y * nx + x);
     usex = ely == kElSymmetry;
   } else if (ox) {
-    if (elx == kElSymmetry) return sG[mx8(q) * n + sy * nx + x];
+    if (elx == kElSymmetry) return (uint32_t)(mx8(q) * n + sy * nx + x);
     usex = true;
   } else {
-    if (ely == kElSymmetry) return sG[my8(q) * n + y * nx + sx];
+    if (ely == kElSymmetry) return (uint32_t)(my8(q) * n + y * nx + sx);
     usex = false;
   }
-  const T o = sG[opp8(q) * n + y * nx + x];
-  return (usex ? elx : ely) == kElDirichlet ? o : -o;  // homogeneous bounce-back rules
+  const uint32_t o = (uint32_t)(opp8(q) * n + y * nx + x);
+  return (usex ? elx : ely) == kElDirichlet ? o : (o | 0x8000u);
 }
+
+// per-cell gather tables of a level: the 8 neighbours of the D(g) stencil
+// (mirror ghosts at walls) and the 8 pull codes, 16 bits each
+struct TailTab {
+  uint32_t dn[4], pl[4];
+};
+
+__device__ __forceinline__ TailTab tail_table(const ProbD& P, int c, int nx, int ny) {
+  TailTab tb;
+  const int n = nx * ny;
+  const int x = c % nx, y = c / nx;
+  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+  uint32_t d[8];
+  int k = 0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx)
+      if (dx != 0 || dy != 0) d[k++] = (uint32_t)(ghost_map(y + dy, ny, pery) * nx + ghost_map(x + dx, nx, perx));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    tb.dn[j] = d[2 * j] | (d[2 * j + 1] << 16);
+    tb.pl[j] = tail_pull_code(2 * j, x, y, nx, ny, P.el, n) | (tail_pull_code(2 * j + 1, x, y, nx, ny, P.el, n) << 16);
+  }
+  return tb;
+}
+
+__device__ __forceinline__ uint32_t lo16(uint32_t w) { return w & 0xffffu; }
+__device__ __forceinline__ uint32_t hi16(uint32_t w) { return w >> 16; }
 
 template <typename T>
 __device__ __forceinline__ ElConst<T> tail_consts(const ProbD& P) {
@@ -726,14 +756,14 @@ __device__ __forceinline__ ElConst<T> tail_consts(const ProbD& P) {
 }
 
 // one application of S on a whole level held by the workgroup: thread t owns
-// cells t, t + 1024, ...; G (iterate) and R (right-hand side) in registers.
-// blend: G <- (1 - gamma) G + gamma S(G); otherwise G <- G - S(G) (residual).
-// Two barriers; sD and sG may be reused right after the return.
+// cells t, t + 1024, ...; G (iterate) and R (right-hand side) in registers,
+// gathers through the level's tables.  blend: G <- (1 - gamma) G + gamma S(G);
+// otherwise G <- G - S(G) (residual).  Two barriers; sD and sG may be reused
+// right after the return.
 template <typename T, int NC>
-__device__ __forceinline__ void tail_relax(const ProbD& P, const ElConst<T>& k, int nx, int ny, T (&G)[NC][8],
+__device__ __forceinline__ void tail_relax(const ElConst<T>& k, int n, const TailTab (&tb)[NC], T (&G)[NC][8],
                                            const T (&R)[NC][8], T* sD, T* sG, bool blend) {
-  const int n = nx * ny, t = threadIdx.x;
-  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+  const int t = threadIdx.x;
 #pragma unroll
   for (int c4 = 0; c4 < NC; ++c4) {
     const int c = t + kTailThreads * c4;
@@ -744,13 +774,16 @@ __device__ __forceinline__ void tail_relax(const ProbD& P, const ElConst<T>& k, 
   for (int c4 = 0; c4 < NC; ++c4) {
     const int c = t + kTailThreads * c4;
     if (c >= n) continue;
-    const int x = c % nx, y = c / nx;
     T v[3][3];
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx)
-        v[dy + 1][dx + 1] = sD[ghost_map(y + dy, ny, pery) * nx + ghost_map(x + dx, nx, perx)];
+    v[0][0] = sD[lo16(tb[c4].dn[0])];
+    v[0][1] = sD[hi16(tb[c4].dn[0])];
+    v[0][2] = sD[lo16(tb[c4].dn[1])];
+    v[1][0] = sD[hi16(tb[c4].dn[1])];
+    v[1][2] = sD[lo16(tb[c4].dn[2])];
+    v[2][0] = sD[hi16(tb[c4].dn[2])];
+    v[2][1] = sD[lo16(tb[c4].dn[3])];
+    v[2][2] = sD[hi16(tb[c4].dn[3])];
+    v[1][1] = T(0);  // the centred gradient does not use the centre
     T gx_, gy_;
     grad_c(v, gx_, gy_);
     T u[8], s8[8];
@@ -766,12 +799,22 @@ __device__ __forceinline__ void tail_relax(const ProbD& P, const ElConst<T>& k, 
   for (int c4 = 0; c4 < NC; ++c4) {
     const int c = t + kTailThreads * c4;
     if (c >= n) continue;
-    const int x = c % nx, y = c / nx;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const T gi = tail_pull<T>(q, x, y, nx, ny, P.el, sG, n);
+      const uint32_t code = (q & 1) ? hi16(tb[c4].pl[q >> 1]) : lo16(tb[c4].pl[q >> 1]);
+      const T v = sG[code & 0x7fffu];
+      const T gi = (code & 0x8000u) ? -v : v;
       G[c4][q] = blend ? omg * G[c4][q] + gam * gi : G[c4][q] - gi;
     }
+  }
+}
+
+template <int NC>
+__device__ __forceinline__ void tail_tables(const ProbD& P, int nx, int ny, TailTab (&tb)[NC]) {
+#pragma unroll
+  for (int c4 = 0; c4 < NC; ++c4) {
+    const int c = threadIdx.x + kTailThreads * c4;
+    if (c < nx * ny) tb[c4] = tail_table(P, c, nx, ny);
   }
 }
 
@@ -810,15 +853,17 @@ __device__ __forceinline__ void tail_descend(const ProbD& P, int l, int K, char*
   T* sD = (T*)lds;
   T* sG = sD + n;
   const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[NC];
+  tail_tables<NC>(P, nx, ny, tb);
   T G[NC][8], R[NC][8];
   tail_load<T, NC>(V, V.r, R);
 #pragma unroll
   for (int c4 = 0; c4 < NC; ++c4)
 #pragma unroll
     for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
-  for (int s = 0; s < K; ++s) tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, true);
+  for (int s = 0; s < K; ++s) tail_relax<T, NC>(k, n, tb, G, R, sD, sG, true);
   tail_store<T, NC>(V, V.gA, G);
-  tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, false);
+  tail_relax<T, NC>(k, n, tb, G, R, sD, sG, false);
   __syncthreads();  // every pull has read sG
 #pragma unroll
   for (int c4 = 0; c4 < NC; ++c4) {
@@ -850,13 +895,15 @@ __device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, char* lds) 
   T* sD = (T*)lds;
   T* sG = sD + V.nx * V.ny;
   const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[NC];
+  tail_tables<NC>(P, V.nx, V.ny, tb);
   T G[NC][8], R[NC][8];
   tail_load<T, NC>(V, V.r, R);
 #pragma unroll
   for (int c4 = 0; c4 < NC; ++c4)
 #pragma unroll
     for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
-  for (int s = 0; s < 2 * K; ++s) tail_relax<T, NC>(P, k, V.nx, V.ny, G, R, sD, sG, true);
+  for (int s = 0; s < 2 * K; ++s) tail_relax<T, NC>(k, V.nx * V.ny, tb, G, R, sD, sG, true);
   tail_store<T, NC>(V, V.gA, G);
   __syncthreads();
 }
@@ -884,7 +931,9 @@ __device__ __forceinline__ void tail_ascend(const ProbD& P, int l, int K, char* 
 #pragma unroll
     for (int q = 0; q < 8; ++q) G[c4][q] += T(ec[q * C.plane + cidx]);
   }
-  for (int s = 0; s < K; ++s) tail_relax<T, NC>(P, k, nx, ny, G, R, sD, sG, true);
+  TailTab tb[NC];
+  tail_tables<NC>(P, nx, ny, tb);
+  for (int s = 0; s < K; ++s) tail_relax<T, NC>(k, n, tb, G, R, sD, sG, true);
   tail_store<T, NC>(V, V.gA, G);
   __syncthreads();
 }
