@@ -11,7 +11,9 @@ the whole grid; inputs are resident in HBM when the timed region starts.
 Beside it: the FP64 path on the same workload and its agreement with the FP32
 result, alpha = 1/2, the batched workload (256 loaded-strip problems of mixed
 size and parameters advanced together), the heterogeneous 2048 x 2048 strip,
-the roofline of the dominant kernel and the FP64 oracle on the host cores.
+a served Poisson stream of solve requests (continuous batching; solves/s and
+p50/p99 latency), the roofline of the dominant kernel and the FP64 oracle on
+the host cores.
 
 Prints one JSON line.  ``--kernel-only`` runs just the dominant kernel's timed
 launches and a plain device copy of known size (the command that the hardware
@@ -199,6 +201,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload and its FP64 twin")
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--het-steps", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=5.0)
+    ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--kernel-only", action="store_true")
     args = ap.parse_args()
@@ -266,6 +270,8 @@ def main():
         s05.close()
         out["alpha_0.5"] = {"value": round(N * (args.steps // 5) / w05 / 1e6, 3), "unit": "MLUPS"}
         out["batched"] = batched(args.batch_steps, 2)
+        from paper_2409_11382_amd import serve
+        out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)

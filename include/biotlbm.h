@@ -183,6 +183,39 @@ bp_status bp_batch_get_fields(bp_batch *b, int32_t i, double *eta, double *p, do
                               int32_t *step);
 bp_status bp_batch_destroy(bp_batch *b);
 
+/* ---- serving: continuous batching of solve requests on one GPU.  The caller
+ * gives one workspace; the server keeps its own area (descriptors and work
+ * lists for up to max_slots problems) at the start and manages the rest as a
+ * pool.  bp_server_submit deep-copies the request's host arrays and queues it.
+ * Each time step of bp_server_advance first admits queued requests in arrival
+ * order while a slot, pool memory (bp_server_request_bytes of the request) and
+ * work-list room are free, writes their initial conditions, then advances
+ * every admitted request by one coupled step in the same launches (levels
+ * aligned from the finest, as in a batch; one captured graph per membership),
+ * and finally retires requests that reached their step count: their fields
+ * are copied to host memory held by the server and their pool memory is
+ * released.  Results are bitwise identical to solving each request alone.
+ * Requests must use the server's precision, K and fixed V-cycle count.
+ * Calls on one server are not thread-safe; all device work runs on hip_stream.
+ *
+ * Request states (bp_server_poll): 0 queued, 1 running, 2 done, 3 failed. */
+typedef struct bp_server bp_server;
+bp_status bp_server_request_bytes(const bp_problem *p, size_t *device_bytes);
+bp_status bp_server_create(void *device_ws, size_t ws_bytes, void *hip_stream, int32_t prec, int32_t K,
+                           int32_t ne_fixed, int32_t max_slots, bp_server **out);
+bp_status bp_server_submit(bp_server *s, const bp_problem *p, int32_t nsteps, int64_t *ticket);
+/* Run up to nsteps time steps (fewer if nothing is left to run); reports the
+ * requests running and queued afterwards. */
+bp_status bp_server_advance(bp_server *s, int32_t nsteps, int32_t *n_active, int32_t *n_queued);
+bp_status bp_server_poll(const bp_server *s, int64_t ticket, int32_t *state, int32_t *steps_done);
+/* Copy the fields of a finished request (eta 2 x N, p N, sigma 3 x N, any may
+ * be NULL; fields at time nsteps dt, as bp_get_fields) and forget the ticket.
+ * A failed request returns its error and is forgotten too. */
+bp_status bp_server_result(bp_server *s, int64_t ticket, double *eta, double *p, double *sigma);
+bp_status bp_server_stats(const bp_server *s, size_t *pool_bytes, size_t *free_bytes, int32_t *n_active,
+                          int32_t *n_queued);
+bp_status bp_server_destroy(bp_server *s);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *bp_last_error(void);
 

@@ -11,6 +11,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -206,12 +208,12 @@ void make_layout(const bp_problem* p, Layout& lo) {
 // entries this problem adds to the engine's tile lists (see engine_upload):
 // schedule lists (full and restriction sets) and inspection lists for every
 // level, its tail entry, the finest level again for the flow step, and the
-// finest level's cell blocks
+// finest level's cell blocks (twice: per-cell kernels and initialisation)
 size_t tile_entries_for(const Layout& lo) {
   size_t t = 1;
   for (int l = 1; l <= lo.L; ++l) t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
-  t += (size_t)cell_blocks(lo.nx, lo.ny);
+  t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
   return t;
 }
 
@@ -326,6 +328,7 @@ struct Prob {
   double last_ratio = -1.0;
   bp_status status = BP_OK;
   int64_t user_id = -1;
+  bool fresh = true;  // initial conditions not yet written
 };
 
 template <typename T>
@@ -519,6 +522,7 @@ struct Engine {
   std::vector<DepthLists> depth;  // per depth
   int fine_off = 0, fine_cnt = 0; // depth-0 full-set tiles of every problem (flow)
   int cell_off = 0, cell_cnt = 0; // finest-level cell blocks
+  int init_off = 0, init_cnt = 0; // cell blocks of the problems still to initialise
   std::vector<Op> step_ops;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
@@ -577,6 +581,14 @@ bp_status engine_upload(Engine& E) {
     for (int b = 0; b < nb; ++b) tiles.push_back(make_int2((int)i, b));
   }
   E.cell_cnt = (int)tiles.size() - E.cell_off;
+  E.init_off = (int)tiles.size();
+  for (size_t i = 0; i < np; ++i) {
+    const Prob& P = *E.probs[i];
+    if (!P.fresh) continue;
+    const int nb = cell_blocks(P.nx, P.ny);
+    for (int b = 0; b < nb; ++b) tiles.push_back(make_int2((int)i, b));
+  }
+  E.init_cnt = (int)tiles.size() - E.init_off;
   if (tiles.size() > E.tiles_cap) return fail(BP_ERR_WORKSPACE, "tile lists exceed the engine area");
   std::vector<int> pids(np);
   for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
@@ -853,6 +865,7 @@ bp_status adaptive_step(Engine& E) {
   return BP_OK;
 }
 
+// initial conditions of every problem of the engine
 bp_status init_states(Engine& E) {
   std::vector<Op> ops{cell_op(E, OP_INIT)};
   BPCHK(run_ops(E, ops));
@@ -860,7 +873,26 @@ bp_status init_states(Engine& E) {
   for (auto* P : E.probs) {
     P->step = 0;
     P->status = BP_OK;
+    P->fresh = false;
   }
+  return BP_OK;
+}
+
+// initial conditions of the problems added since the last upload only (the
+// others keep their state)
+bp_status init_fresh(Engine& E) {
+  if (E.init_cnt == 0) return BP_OK;
+  Op o = cell_op(E, OP_INIT);
+  o.cl.tiles = E.d_tiles + E.init_off;
+  o.count = E.init_cnt;
+  std::vector<Op> ops{o};
+  BPCHK(run_ops(E, ops));
+  for (auto* P : E.probs)
+    if (P->fresh) {
+      P->step = 0;
+      P->status = BP_OK;
+      P->fresh = false;
+    }
   return BP_OK;
 }
 
@@ -903,6 +935,130 @@ struct bp_solver {
 struct bp_batch {
   Engine E;
   std::vector<Prob> P;
+};
+
+namespace {
+
+// a request's problem, deep-copied so that the caller's arrays may go away
+// after bp_server_submit
+struct HostProblem {
+  bp_problem p{};
+  std::vector<double> kappa, body, src;
+  std::vector<int8_t> ftype[4];
+  std::vector<double> elv[4], pv[4];
+
+  explicit HostProblem(const bp_problem* q) : p(*q) {
+    const size_t N = (size_t)q->nx * q->ny;
+    if (q->kappa) {
+      kappa.assign(q->kappa, q->kappa + N);
+      p.kappa = kappa.data();
+    }
+    if (q->body_f) {
+      body.assign(q->body_f, q->body_f + 2 * N);
+      p.body_f = body.data();
+    }
+    if (q->source_s) {
+      src.assign(q->source_s, q->source_s + N);
+      p.source_s = src.data();
+    }
+    for (int k = 0; k < 4; ++k) {
+      const size_t n = (size_t)side_len(k, q->nx, q->ny);
+      const bp_side& sd = q->side[k];
+      if (sd.flow_type) {
+        ftype[k].assign(sd.flow_type, sd.flow_type + n);
+        p.side[k].flow_type = ftype[k].data();
+      }
+      if (sd.el_value) {
+        elv[k].assign(sd.el_value, sd.el_value + 2 * n);
+        p.side[k].el_value = elv[k].data();
+      }
+      if (sd.p_value) {
+        pv[k].assign(sd.p_value, sd.p_value + n);
+        p.side[k].p_value = pv[k].data();
+      }
+    }
+  }
+  HostProblem(const HostProblem&) = delete;
+  HostProblem& operator=(const HostProblem&) = delete;
+};
+
+// first-fit allocator over byte offsets of the server's pool; adjacent free
+// blocks are merged on release
+class Pool {
+ public:
+  void init(size_t off, size_t size) {
+    free_.clear();
+    if (size) free_[off] = size;
+    total_ = size;
+  }
+  bool alloc(size_t bytes, size_t& off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      off = it->first;
+      const size_t rest = it->second - bytes;
+      free_.erase(it);
+      if (rest) free_[off + bytes] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t total() const { return total_; }
+  size_t free_bytes() const {
+    size_t t = 0;
+    for (const auto& kv : free_) t += kv.second;
+    return t;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t total_ = 0;
+};
+
+enum { kReqQueued = 0, kReqRunning = 1, kReqDone = 2, kReqFailed = 3 };
+
+struct SrvReq {
+  int64_t ticket = 0;
+  std::unique_ptr<HostProblem> hp;
+  int nsteps = 0;
+  int state = kReqQueued;
+  Layout lo;
+  size_t tiles = 0;
+  Prob P;
+  size_t off = 0;
+  std::vector<double> eta, p, sigma;
+  bp_status status = BP_OK;
+  std::string error;
+};
+
+}  // namespace
+
+struct bp_server {
+  Engine E;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Pool pool;
+  int prec = 0, K = 4, ne = 3, max_slots = 0;
+  size_t tiles_cap = 0, tiles_used = 0;
+  int64_t next_ticket = 1;
+  std::deque<SrvReq*> queue;
+  std::vector<SrvReq*> active;
+  std::map<int64_t, std::unique_ptr<SrvReq>> reqs;
+  bool dirty = false;
 };
 
 namespace {
@@ -1309,6 +1465,190 @@ bp_status bp_batch_destroy(bp_batch* b) {
   if (!b) return BP_OK;
   engine_release(b->E);
   delete b;
+  return BP_OK;
+}
+
+// ------------------------------------------------------------------ server
+bp_status bp_server_request_bytes(const bp_problem* p, size_t* device_bytes) {
+  BPCHK(validate(p));
+  if (!device_bytes) return fail(BP_ERR_ARG, "null output");
+  Layout lo;
+  make_layout(p, lo);
+  *device_bytes = lo.total;
+  return BP_OK;
+}
+
+bp_status bp_server_create(void* device_ws, size_t ws_bytes, void* hip_stream, int32_t prec, int32_t K,
+                           int32_t ne_fixed, int32_t max_slots, bp_server** out) {
+  if (!out) return fail(BP_ERR_ARG, "null output handle");
+  *out = nullptr;
+  if (prec < BP_FP64 || prec > BP_FP64_SHIFTED || K < 1 || ne_fixed < 1 || max_slots < 1)
+    return fail(BP_ERR_ARG, "bad server parameters");
+  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0) return fail(BP_ERR_WORKSPACE, "workspace missing or misaligned");
+  const size_t tiles_cap = std::max<size_t>(65536, ws_bytes / 2048);
+  const size_t area = engine_bytes((size_t)max_slots, tiles_cap);
+  if (ws_bytes <= area) return fail(BP_ERR_WORKSPACE, "workspace smaller than the server's own area");
+  bp_server* s = new bp_server();
+  s->ws = (char*)device_ws;
+  s->ws_bytes = ws_bytes;
+  s->prec = prec;
+  s->K = K;
+  s->ne = ne_fixed;
+  s->max_slots = max_slots;
+  s->tiles_cap = tiles_cap;
+  const bool fdbl = prec == BP_FP64 || prec == BP_FP64_SHIFTED;
+  const bool shift = prec == BP_FP32_SHIFTED || prec == BP_FP64_SHIFTED;
+  bp_status rc = engine_init(s->E, s->ws, area, (size_t)max_slots, tiles_cap, (hipStream_t)hip_stream, fdbl, shift,
+                             K, ne_fixed);
+  if (rc != BP_OK) {
+    engine_release(s->E);
+    delete s;
+    return rc;
+  }
+  s->pool.init(area, ws_bytes - area);
+  *out = s;
+  return BP_OK;
+}
+
+bp_status bp_server_submit(bp_server* s, const bp_problem* p, int32_t nsteps, int64_t* ticket) {
+  if (!s || !p || !ticket || nsteps < 1) return fail(BP_ERR_ARG, "bad request arguments");
+  BPCHK(validate(p));
+  if (p->prec != s->prec || p->K != s->K || p->ne_fixed != s->ne)
+    return fail(BP_ERR_ARG, "a request must use the server's precision, K and fixed V-cycle count");
+  auto r = std::make_unique<SrvReq>();
+  make_layout(p, r->lo);
+  r->tiles = tile_entries_for(r->lo);
+  if (r->lo.total > s->pool.total() || r->tiles > s->tiles_cap)
+    return fail(BP_ERR_WORKSPACE, "the request can never fit the server's workspace");
+  r->hp = std::make_unique<HostProblem>(p);
+  r->nsteps = nsteps;
+  r->ticket = s->next_ticket++;
+  *ticket = r->ticket;
+  s->queue.push_back(r.get());
+  s->reqs[r->ticket] = std::move(r);
+  return BP_OK;
+}
+
+namespace {
+
+void server_retire(bp_server* s, SrvReq* r) {
+  s->pool.release(r->off, r->lo.total);
+  s->tiles_used -= r->tiles;
+  s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+  s->dirty = true;
+}
+
+// admit queued requests in arrival order while slots, pool memory and tile
+// list capacity allow
+bp_status server_admit(bp_server* s) {
+  while (!s->queue.empty() && (int)s->active.size() < s->max_slots) {
+    SrvReq* r = s->queue.front();
+    if (s->tiles_used + r->tiles > s->tiles_cap) break;
+    size_t off = 0;
+    if (!s->pool.alloc(r->lo.total, off)) break;
+    s->queue.pop_front();
+    r->off = off;
+    bp_status rc = setup_problem(&r->hp->p, r->lo, s->ws + off, s->E.stream, r->P);
+    if (rc != BP_OK) {
+      s->pool.release(off, r->lo.total);
+      r->state = kReqFailed;
+      r->status = rc;
+      r->error = bp_last_error();
+      continue;
+    }
+    r->P.fresh = true;
+    r->state = kReqRunning;
+    s->tiles_used += r->tiles;
+    s->active.push_back(r);
+    s->dirty = true;
+  }
+  return BP_OK;
+}
+
+bp_status server_sync_members(bp_server* s) {
+  if (!s->dirty) return BP_OK;
+  s->E.probs.clear();
+  for (SrvReq* r : s->active) s->E.probs.push_back(&r->P);
+  BPCHK(engine_upload(s->E));
+  BPCHK(init_fresh(s->E));
+  s->dirty = false;
+  return BP_OK;
+}
+
+}  // namespace
+
+bp_status bp_server_advance(bp_server* s, int32_t nsteps, int32_t* n_active, int32_t* n_queued) {
+  if (!s || nsteps < 0) return fail(BP_ERR_ARG, "bad server arguments");
+  for (int k = 0; k < nsteps; ++k) {
+    BPCHK(server_admit(s));
+    BPCHK(server_sync_members(s));
+    if (s->active.empty()) break;
+    BPCHK(fixed_step(s->E));
+    std::vector<SrvReq*> done;
+    for (SrvReq* r : s->active)
+      if (r->P.step >= r->nsteps) done.push_back(r);
+    if (done.empty()) continue;
+    BPCHK(extract_fields(s->E));
+    for (SrvReq* r : done) {
+      const size_t N = (size_t)r->P.nx * r->P.ny;
+      r->eta.resize(2 * N);
+      r->p.resize(N);
+      r->sigma.resize(3 * N);
+      bp_status rc = fields_of(s->E, r->P, r->eta.data(), r->p.data(), r->sigma.data(), nullptr);
+      r->state = rc == BP_OK ? kReqDone : kReqFailed;
+      r->status = rc;
+      if (rc != BP_OK) r->error = bp_last_error();
+      server_retire(s, r);
+    }
+  }
+  if (n_active) *n_active = (int32_t)s->active.size();
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  return BP_OK;
+}
+
+bp_status bp_server_poll(const bp_server* s, int64_t ticket, int32_t* state, int32_t* steps_done) {
+  if (!s) return fail(BP_ERR_ARG, "null server");
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(BP_ERR_ARG, "unknown ticket");
+  const SrvReq& r = *it->second;
+  if (state) *state = r.state;
+  if (steps_done) *steps_done = r.state == kReqQueued ? 0 : (r.state == kReqRunning ? r.P.step : r.nsteps);
+  return BP_OK;
+}
+
+bp_status bp_server_result(bp_server* s, int64_t ticket, double* eta, double* p, double* sigma) {
+  if (!s) return fail(BP_ERR_ARG, "null server");
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(BP_ERR_ARG, "unknown ticket");
+  SrvReq& r = *it->second;
+  if (r.state == kReqQueued || r.state == kReqRunning) return fail(BP_ERR_STATE, "the request has not finished");
+  if (r.state == kReqFailed) {
+    const bp_status st = r.status == BP_OK ? BP_ERR_STATE : r.status;
+    const std::string msg = "request failed: " + r.error;
+    s->reqs.erase(it);
+    return fail(st, msg);
+  }
+  if (eta) std::memcpy(eta, r.eta.data(), r.eta.size() * sizeof(double));
+  if (p) std::memcpy(p, r.p.data(), r.p.size() * sizeof(double));
+  if (sigma) std::memcpy(sigma, r.sigma.data(), r.sigma.size() * sizeof(double));
+  s->reqs.erase(it);
+  return BP_OK;
+}
+
+bp_status bp_server_stats(const bp_server* s, size_t* pool_bytes, size_t* free_bytes, int32_t* n_active,
+                          int32_t* n_queued) {
+  if (!s) return fail(BP_ERR_ARG, "null server");
+  if (pool_bytes) *pool_bytes = s->pool.total();
+  if (free_bytes) *free_bytes = s->pool.free_bytes();
+  if (n_active) *n_active = (int32_t)s->active.size();
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  return BP_OK;
+}
+
+bp_status bp_server_destroy(bp_server* s) {
+  if (!s) return BP_OK;
+  engine_release(s->E);
+  delete s;
   return BP_OK;
 }
 

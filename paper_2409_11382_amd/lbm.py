@@ -80,6 +80,14 @@ def load_library():
             "bp_batch_step": [vp, i32],
             "bp_batch_get_fields": [vp, i32, dp, dp, dp, C.POINTER(i32)],
             "bp_batch_destroy": [vp],
+            "bp_server_request_bytes": [C.POINTER(_Problem), C.POINTER(C.c_size_t)],
+            "bp_server_create": [vp, C.c_size_t, vp, i32, i32, i32, i32, C.POINTER(vp)],
+            "bp_server_submit": [vp, C.POINTER(_Problem), i32, C.POINTER(C.c_int64)],
+            "bp_server_advance": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
+            "bp_server_poll": [vp, C.c_int64, C.POINTER(i32), C.POINTER(i32)],
+            "bp_server_result": [vp, C.c_int64, dp, dp, dp],
+            "bp_server_stats": [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(i32), C.POINTER(i32)],
+            "bp_server_destroy": [vp],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -324,3 +332,89 @@ class Batch:
         _check(self._lib.bp_batch_get_fields(self._h, int(i), _dptr(eta), _dptr(pr), _dptr(sig), C.byref(st)),
                "bp_batch_get_fields")
         return dict(eta=eta, p=pr, sigma=sig, step=st.value)
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+def request_bytes(p: Problem, prec="fp32_shifted") -> int:
+    """Device bytes a request occupies in a server's pool (host-only)."""
+    lib = load_library()
+    pb, _keep = marshal_problem(p, prec)
+    n = C.c_size_t(0)
+    _check(lib.bp_server_request_bytes(C.byref(pb), C.byref(n)), "bp_server_request_bytes")
+    return n.value
+
+
+class Server:
+    """Continuous batching of solve requests on one GPU (bp_server_*): queued
+    requests are admitted by pool memory as earlier ones finish, and all
+    admitted requests advance together.  Method names follow biotlbm.h."""
+
+    def __init__(self, ws_bytes: int, prec="fp32_shifted", K=4, ne_fixed=3, max_slots=512, device="cuda:0",
+                 stream=None):
+        import torch
+
+        lib = load_library()
+        self.prec = prec
+        self.K, self.ne_fixed = K, ne_fixed
+        self.device = torch.device(device)
+        self.ws_bytes = int(ws_bytes) // 256 * 256
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.ws.record_stream(self.stream)
+        h = C.c_void_p(0)
+        _check(lib.bp_server_create(C.c_void_p(self.ws.data_ptr()), self.ws_bytes, C.c_void_p(self.stream.cuda_stream),
+                                    PREC_NAMES[prec], int(K), int(ne_fixed), int(max_slots), C.byref(h)),
+               "bp_server_create")
+        self._h = h
+        self._lib = lib
+        self._shape = {}
+
+    def submit(self, p: Problem, nsteps: int) -> int:
+        p = p.replace(K=self.K, ne_fixed=self.ne_fixed)
+        pb, keep = marshal_problem(p, self.prec)
+        t = C.c_int64(0)
+        _check(self._lib.bp_server_submit(self._h, C.byref(pb), int(nsteps), C.byref(t)), "bp_server_submit")
+        del keep
+        self._shape[t.value] = (p.nx, p.ny)
+        return t.value
+
+    def advance(self, nsteps=1):
+        a, q = C.c_int32(0), C.c_int32(0)
+        _check(self._lib.bp_server_advance(self._h, int(nsteps), C.byref(a), C.byref(q)), "bp_server_advance")
+        return a.value, q.value
+
+    def poll(self, ticket: int):
+        st, n = C.c_int32(0), C.c_int32(0)
+        _check(self._lib.bp_server_poll(self._h, int(ticket), C.byref(st), C.byref(n)), "bp_server_poll")
+        return st.value, n.value
+
+    def result(self, ticket: int):
+        nx, ny = self._shape[ticket]
+        eta = np.zeros((2, ny, nx))
+        p = np.zeros((ny, nx))
+        sig = np.zeros((3, ny, nx))
+        rc = self._lib.bp_server_result(self._h, int(ticket), _dptr(eta), _dptr(p), _dptr(sig))
+        if rc != BP_ERR_STATE:  # the library forgets the ticket unless it is still running
+            self._shape.pop(ticket, None)
+        _check(rc, "bp_server_result")
+        return {"eta": eta, "p": p, "sigma": sig}
+
+    def stats(self):
+        pool, free = C.c_size_t(0), C.c_size_t(0)
+        a, q = C.c_int32(0), C.c_int32(0)
+        _check(self._lib.bp_server_stats(self._h, C.byref(pool), C.byref(free), C.byref(a), C.byref(q)),
+               "bp_server_stats")
+        return {"pool_bytes": pool.value, "free_bytes": free.value, "active": a.value, "queued": q.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.bp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

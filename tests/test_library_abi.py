@@ -53,3 +53,13 @@ def test_last_error_message():
     with pytest.raises(L.BiotError):
         L.workspace_bytes(P.loaded_strip(n=16).replace(c0=-1.0))
     assert b"c0" in lib.bp_last_error()
+
+
+def test_server_request_bytes_is_host_only():
+    a = L.request_bytes(P.loaded_strip(n=64), "fp32_shifted")
+    b = L.request_bytes(P.loaded_strip(n=128), "fp32_shifted")
+    assert 0 < a < b and a % 256 == 0
+    # a request's footprint is its problem's part of a lone solver's workspace
+    assert a < L.workspace_bytes(P.loaded_strip(n=64), "fp32_shifted")
+    with pytest.raises(L.BiotError):
+        L.request_bytes(P.loaded_strip(n=64).replace(c0=0.0))
