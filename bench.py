@@ -33,7 +33,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_device.h", "lbm_engine.h")
+# the kernel and the host code that orders its work lists (XCD-aware tile order)
+KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_device.h", "lbm_engine.h", "biotlbm.cpp")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fine_sweep_fp32_shifted_512.txt")
 COPY_BYTES = 256 << 20
 

@@ -526,6 +526,7 @@ struct Engine {
   std::vector<Op> step_ops;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
+  bool xcd_order = true;
   double* host_pin = nullptr;
 };
 
@@ -535,6 +536,23 @@ int tgroup(const Engine& E, const Prob& P, int depth) {
   if (l == 1 && P.L > 1) return 2;      // FP64 coarsest level
   if (l == 2) return 1;                 // FP32 level with an FP64 coarser level
   return 0;
+}
+
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (block i runs on
+// XCD i mod 8) and each XCD has its own L2.  Reordering a list segment so that
+// XCD k receives a contiguous run of its row-major tiles keeps neighbouring
+// tiles, which share halo rows and columns, on one L2.
+constexpr int kXcds = 8;
+void xcd_order(std::vector<int2>& tiles, size_t off) {
+  const size_t n = tiles.size() - off;
+  if (n <= (size_t)kXcds) return;
+  std::vector<int2> seg(tiles.begin() + off, tiles.end());
+  size_t start = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    const size_t cnt = n / kXcds + ((size_t)x < n % kXcds ? 1 : 0);
+    for (size_t k = 0; k < cnt; ++k) tiles[off + k * kXcds + x] = seg[start + k];
+    start += cnt;
+  }
 }
 
 // write descriptors and tile lists for the current problem set
@@ -560,6 +578,7 @@ bp_status engine_upload(Engine& E) {
           const int nt = sweep_tiles(P.lo.lv[l].nx, P.lo.lv[l].ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
+        if (E.xcd_order) xcd_order(tiles, E.depth[d].off[set][g]);
         E.depth[d].cnt[set][g] = (int)tiles.size() - E.depth[d].off[set][g];
       }
     E.depth[d].tail_off = (int)tiles.size();
@@ -573,6 +592,7 @@ bp_status engine_upload(Engine& E) {
     const int nt = sweep_tiles(P.nx, P.ny);
     for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
   }
+  if (E.xcd_order) xcd_order(tiles, E.fine_off);
   E.fine_cnt = (int)tiles.size() - E.fine_off;
   E.cell_off = (int)tiles.size();
   for (size_t i = 0; i < np; ++i) {
@@ -791,6 +811,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   E.K = K;
   E.ne = ne;
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
   return BP_OK;
