@@ -129,8 +129,8 @@ struct Layout {
   bool fdbl = true, shift = false;
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
-  size_t off_eta, off_sig, off_part, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
-  int ntiles_fine = 0;
+  size_t off_eta, off_sig, off_part, off_part2, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
+  int ntiles_fine = 0, ntiles_fine2 = 0;
   int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
   size_t total = 0;
 };
@@ -193,6 +193,8 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
   lo.tail_depth = tail_depth_of(lo);
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
+  lo.ntiles_fine2 = sweep2_tiles(p->nx, p->ny, lo.fdbl);
+  lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
   for (int s = 0; s < 4; ++s) {
     const int n = side_len(s, p->nx, p->ny);
@@ -206,12 +208,13 @@ void make_layout(const bp_problem* p, Layout& lo) {
 // bytes of the engine's own area (descriptors and work lists) for a set of
 // problems
 // entries this problem adds to the engine's tile lists (see engine_upload):
-// schedule lists (full and restriction sets) and inspection lists for every
-// level, its tail entry, the finest level again for the flow step, and the
+// schedule lists (full and restriction sets), inspection lists and
+// two-application lists for every level, its tail entry, the finest level again for the flow step, and the
 // finest level's cell blocks (twice: per-cell kernels and initialisation)
 size_t tile_entries_for(const Layout& lo) {
   size_t t = 1;
-  for (int l = 1; l <= lo.L; ++l) t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
+  for (int l = 1; l <= lo.L; ++l)
+    t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4 + sweep2_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl);
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
   return t;
@@ -410,6 +413,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.lv[l].ny = v.ny;
     d.lv[l].pitch = v.pitch;
     d.lv[l].tiles_x = sweep_tiles_x(v.nx);
+    d.lv[l].tiles_x2 = sweep2_tiles_x(v.nx);
     d.lv[l].dbl = v.dbl ? 1 : 0;
     d.lv[l].plane = v.plane;
   }
@@ -438,6 +442,8 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.eta = (double*)(base + lo.off_eta);
   d.sig = (double*)(base + lo.off_sig);
   d.partials = (double*)(base + lo.off_part);
+  d.partials2 = (double*)(base + lo.off_part2);
+  d.ntiles_fine2 = lo.ntiles_fine2;
   d.norm2 = (double*)(base + lo.off_scal);
   d.phase = (int*)(base + lo.off_scal + 32);
   d.flags = (int*)(base + lo.off_scal + 40);
@@ -487,6 +493,7 @@ enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_A
 struct Op {
   OpKind kind;
   int mode = 0;           // sweep mode
+  bool fused = false;     // two smoothing applications per launch
   int tdbl = 0, cdbl = 0; // sweep storage types (level, coarser level)
   bool shift = false;
   SweepL sw{};
@@ -500,10 +507,12 @@ struct Op {
 // storage groups (level FP32 / coarser FP32, FP32 / FP64, FP64 / FP64)
 // set 0: full set of the time-step schedule (problems not inside their coarse
 // tail at this depth), set 1: its restriction set (problems with a coarser
-// level), sets 2 and 3: the same without the tail (inspection operations)
+// level), sets 2 and 3: the same without the tail (inspection operations),
+// set 4: set 0 in the tiles of the two-application sweep
+constexpr int kSetFused = 4;
 struct DepthLists {
-  int off[4][3] = {};
-  int cnt[4][3] = {};
+  int off[5][3] = {};
+  int cnt[5][3] = {};
   int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
@@ -527,6 +536,7 @@ struct Engine {
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
   bool xcd_order = true;
+  bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   double* host_pin = nullptr;
 };
 
@@ -566,16 +576,17 @@ bp_status engine_upload(Engine& E) {
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
-    for (int set = 0; set < 4; ++set)
+    for (int set = 0; set < 5; ++set)
       for (int g = 0; g < 3; ++g) {
         E.depth[d].off[set][g] = (int)tiles.size();
         for (size_t i = 0; i < np; ++i) {
           const Prob& P = *E.probs[i];
           const int l = P.L - d;
           const int td = P.lo.tail_depth;
-          if (l < 1 || ((set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
-          if (set < 2 && td > 0 && d >= td) continue;  // inside the problem's coarse tail
-          const int nt = sweep_tiles(P.lo.lv[l].nx, P.lo.lv[l].ny);
+          if (l < 1 || (set < 4 && (set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
+          if ((set < 2 || set == kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
+          const LevelLay& v = P.lo.lv[l];
+          const int nt = set == kSetFused ? sweep2_tiles(v.nx, v.ny, v.dbl) : sweep_tiles(v.nx, v.ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
         if (E.xcd_order) xcd_order(tiles, E.depth[d].off[set][g]);
@@ -630,6 +641,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     if (cnt == 0) continue;
     Op o;
     o.kind = OP_SWEEP;
+    o.fused = set == kSetFused;
     o.mode = mode;
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
@@ -646,13 +658,37 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
   }
 }
 
+// `count` smoothing applications at depth d, ping-ponging from buffer `sel`:
+// with fusion, pairs of applications run in one two-application launch, a
+// single launch takes an odd remainder first.  Only the first launch may read
+// a zero input or add the coarse correction, only the last writes the norm
+// partials.  Returns the buffer holding the result.
+int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, int sel, bool zero_in, bool prolong,
+                  bool partials, bool fuse) {
+  bool first = true;
+  while (count > 0) {
+    const bool pair = fuse && count >= 2 && (count % 2 == 0);
+    const int in = (first && zero_in) ? 2 : sel;
+    const int pro = (first && prolong) ? 1 : 0;
+    count -= pair ? 2 : 1;
+    const int part = (partials && count == 0) ? 1 : 0;
+    add_sweeps(E, ops, d, pair ? kSetFused : set, kSmooth, in, 1 - sel, pro, part);
+    sel = 1 - sel;
+    first = false;
+  }
+  return sel;
+}
+
 // Algorithm 4 at depth d for every problem that has a level there.  The
 // iterate of a level starts in buffer A (zero at coarse depths) and ends in A
-// after its 2K smoothing sweeps.  first_done: the first pre-smoothing sweep
-// was already issued (adaptive mode).  tail: problems whose coarse tail starts
-// at this depth run it in one launch (time-step schedule); without it every
-// level is swept by the tile kernels (inspection operations).
-void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true) {
+// after its 2K smoothing applications (the pre- and post-smoothing runs take
+// the same number of launches).  first_done: the first pre-smoothing sweep was
+// already issued (adaptive mode).  tail: problems whose coarse tail starts at
+// this depth run it in one launch (time-step schedule); without it every level
+// is swept by the tile kernels (inspection operations).  fuse: pairs of
+// smoothing applications per launch.
+void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true,
+                bool fuse = false) {
   if (d >= E.maxL) return;
   const int full = tail ? 0 : 2, restr = full + 1;
   if (tail && E.depth[d].tail_cnt > 0) {
@@ -668,22 +704,21 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
   bool here = false;
   for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
   if (!here) return;
+  fuse = fuse && tail && !first_done;
   int sel = 0;
-  for (int k = 0; k < E.K; ++k) {
-    if (!(k == 0 && first_done)) add_sweeps(E, ops, d, full, kSmooth, (d > 0 && k == 0) ? 2 : sel, 1 - sel, 0, 0);
-    sel = 1 - sel;
+  if (first_done) {
+    // the first pre-smoothing application (A -> B) was issued separately
+    sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, false);
+  } else {
+    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0, false, false, fuse);
   }
   bool deeper = false;
   for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   if (deeper) {
     add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
-    add_vcycle(E, ops, d + 1, false, false, tail);
+    add_vcycle(E, ops, d + 1, false, false, tail, fuse);
   }
-  for (int k = 0; k < E.K; ++k) {
-    const int part = (partials_last && d == 0 && k == E.K - 1) ? 1 : 0;
-    add_sweeps(E, ops, d, full, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, part);
-    sel = 1 - sel;
-  }
+  add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse);
 }
 
 Op cell_op(Engine& E, OpKind k) {
@@ -716,14 +751,23 @@ void build_step_ops(Engine& E) {
   ops.clear();
   if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
   ops.push_back(cell_op(E, OP_FORCE));
-  for (int j = 0; j < E.ne; ++j) add_vcycle(E, ops, 0, false, j == E.ne - 1);
-  if (E.ne > 0) ops.push_back(prob_op(E, OP_FINALIZE));
+  for (int j = 0; j < E.ne; ++j) add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse);
+  if (E.ne > 0) {
+    Op f = prob_op(E, OP_FINALIZE);
+    f.pl.fused = (E.fuse && E.K >= 2) ? 1 : 0;  // the last post-smoothing launch was a pair
+    ops.push_back(f);
+  }
   ops.push_back(flow_op(E));
   ops.push_back(prob_op(E, OP_ADVANCE));
 }
 
 template <typename T, typename Tc>
 hipError_t sweep_launch(const Op& o, hipStream_t s) {
+  if (o.fused) {
+    if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false>(o.sw, o.count, s);
+    return o.shift ? launch_tsweep2<T, Tc, true, true>(o.sw, o.count, s)
+                   : launch_tsweep2<T, Tc, true, false>(o.sw, o.count, s);
+  }
   if (o.shift) {
     switch (o.mode) {
       case kSmooth: return launch_tsweep<T, Tc, kSmooth, true>(o.sw, o.count, s);
@@ -812,6 +856,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   E.ne = ne;
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
   return BP_OK;
@@ -1336,6 +1381,7 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
   std::vector<Op> ops;
   switch (which) {
     case 0: add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 0); break;
+    case 4: add_sweeps(E, ops, 0, kSetFused, kSmooth, 0, 1, 0, 0); break;
     case 1:
       if (P.L < 2) return fail(BP_ERR_ARG, "no coarser level");
       add_sweeps(E, ops, 0, 1, kRestrict, 0, 0, 0, 0);
@@ -1387,7 +1433,8 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
   *avg_us = 1000.0 * ms / iters;
   double b;
   switch (which) {
-    case 0: b = N * (16.0 + 2.0 + 2.0 * shift) * es; break;
+    case 0:
+    case 4: b = N * (16.0 + 2.0 + 2.0 * shift) * es; break;
     case 1: {
       const double ce = P.lo.lv[P.L - 1].dbl ? 8.0 : 4.0;
       b = N * (8.0 + 2.0 + 2.0 * shift) * es + (N / 4.0) * 8.0 * ce;

@@ -27,6 +27,7 @@ struct LevelD {
   void* r;           // coarse right-hand side (8 planes), null on the finest level
   int nx, ny, pitch;
   int tiles_x;       // sweep tiles along x: ceil(nx / kTileX)
+  int tiles_x2;      // two-application sweep tiles along x: ceil(nx / kTile2X)
   int dbl;           // FP64 storage
   int64_t plane;
 };
@@ -51,12 +52,14 @@ struct ProbD {
   double* eta;                // extraction output (2 dense planes)
   double* sig;                // extraction output (3 dense planes)
   double* partials;           // per finest-level tile: sum rho^2, sum g^2
+  double* partials2;          // the same per two-application tile
   double* norm2;              // finalized sums
   int* phase;                 // completed steps (device copy)
   int* flags;                 // [0] non-finite seen
   double om_s, om_d, beta22, kD, cstar, gamma;
   double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
   int ntiles_fine;            // sweep tiles of the finest level
+  int ntiles_fine2;           // two-application sweep tiles of the finest level
 };
 
 struct SweepL {
@@ -77,6 +80,7 @@ struct CellL {    // per-cell kernels over the finest level
 struct ProbL {    // one block per problem
   const ProbD* probs;
   const int* pids;
+  int fused;      // finalize: partials of the two-application sweep
 };
 
 // Coarse "tail" of the multigrid recursion: one 1024-thread workgroup per
@@ -97,6 +101,12 @@ struct TailL {
 
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
+// two smoothing applications per launch: 56 x (4 NK - 8) output tiles
+constexpr int kTile2X = kWave - 8;
+constexpr int kNK2F32 = 5;   // 12 output rows in FP32 storage
+constexpr int kNK2F64 = 4;   // 8 output rows in FP64 storage
+template <typename T, typename Tc, bool FINE, bool SHIFT>
+hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
@@ -116,6 +126,11 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 
 inline int sweep_tiles_x(int nx) { return (nx + kTileX - 1) / kTileX; }
 inline int sweep_tiles(int nx, int ny) { return sweep_tiles_x(nx) * ((ny + kTileY - 1) / kTileY); }
+inline int sweep2_tiles_x(int nx) { return (nx + kTile2X - 1) / kTile2X; }
+inline int sweep2_tiles(int nx, int ny, bool dbl) {
+  const int ty = 4 * (dbl ? kNK2F64 : kNK2F32) - 8;
+  return sweep2_tiles_x(nx) * ((ny + ty - 1) / ty);
+}
 inline int cell_blocks(int nx, int ny) { return ((nx + kCellBX - 1) / kCellBX) * ((ny + kCellBY - 1) / kCellBY); }
 
 }  // namespace biot

@@ -287,6 +287,276 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 }
 
 // ======================================================================
+// two smoothing applications in one launch
+// ======================================================================
+// Same arithmetic as two k_tsweep smoothing launches.  The tile loads a
+// 64-column region with a halo of 4 (56 output columns, TY = 4 NK - 8 output
+// rows); each wave keeps its NK rows in registers across both applications,
+// whose valid region shrinks by 2 per application (D and collision need one
+// neighbour, the pull one more).  Between the applications only the first
+// ghost row/column of D must be restored by reflection (the loaded ghosts were
+// reflected copies; after the first application they hold unused values):
+// columns by a lane permutation, rows through LDS.  The intermediate iterate
+// of real cells outside the domain's periodic wrap is never needed.
+template <typename T, typename Tc, bool FINE, bool SHIFT>
+__global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
+  constexpr int NK = sizeof(T) == 8 ? kNK2F64 : kNK2F32;
+  constexpr int RR = 4 * NK;     // region rows (four halo rows each side)
+  constexpr int TY = RR - 8;     // output rows
+  __shared__ T sD[RR][kWave];
+  __shared__ T sS[8][RR - 2][kWave];
+  __shared__ T sE[SHIFT ? 2 : 1][SHIFT ? RR : 1][kWave];
+  __shared__ double sRed[8];
+
+  const int2 te = a.tiles[blockIdx.x];
+  const ProbD& P = a.probs[te.x];
+  const int l = P.L - a.depth;
+  const LevelD& V = P.lv[l];
+  const int nx = V.nx, ny = V.ny, pitch = V.pitch;
+  const int64_t plane = V.plane;
+  const int tx = te.y % V.tiles_x2, ty = te.y / V.tiles_x2;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int x = tx * kTile2X - 4 + lane;
+  const int y0 = ty * TY;
+  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+  // a single reflection covers ghosts up to nx cells out; farther ones (levels
+  // narrower than the halo) never reach a real cell and stay zero
+  const bool col_ok = x >= -4 && x < nx + 4 && (perx || (x >= -nx && x < 2 * nx));
+  const int gx = col_ok ? ghost_map(x, nx, perx) : 0;
+  const bool xreal = col_ok && (perx || (x >= 0 && x < nx));
+  const T* gin = a.in_sel == 2 ? nullptr : (const T*)(a.in_sel ? V.gB : V.gA);
+  T* gout = (T*)(a.out_sel ? V.gB : V.gA);
+  const T* rr = FINE ? nullptr : (const T*)V.r;
+  const T* Ft = FINE ? (const T*)P.Ft : nullptr;
+  const bool pro = a.prolong && l > 1;
+  const Tc* ec = pro ? (const Tc*)P.lv[l - 1].gA : nullptr;
+  const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
+  const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
+  const T* eref = SHIFT ? (const T*)P.eref : nullptr;
+  ElConst<T> k;
+  k.om_s = T(P.om_s);
+  k.om_d = T(P.om_d);
+  k.beta22 = T(P.beta22);
+  k.kD = T(P.kD);
+  k.cstar = T(P.cstar);
+  k.gamma = T(P.gamma);
+
+  T G[NK][8];
+  T Rv[FINE ? 1 : NK][8];
+  T Fx[FINE ? NK : 1], Fy[FINE ? NK : 1];
+
+  // ---- load the region (ghosts as reflected or periodic copies)
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    const int j = w + 4 * kk;
+    const int y = y0 - 4 + j;
+    const bool ok = col_ok && y >= -4 && y < ny + 4 && (pery || (y >= -ny && y < 2 * ny));
+    const int gy = ok ? ghost_map(y, ny, pery) : 0;
+    const int64_t idx = (int64_t)gy * pitch + gx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[kk][q] = (ok && gin) ? gin[q * plane + idx] : T(0);
+    if (ok && pro) {
+      const int64_t cidx = (int64_t)(gy >> 1) * cpitch + (gx >> 1);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) G[kk][q] += T(ec[q * cplane + cidx]);
+    }
+    const bool crow = j >= 1 && j < RR - 1;
+    if (FINE) {
+      Fx[kk] = (ok && crow) ? Ft[idx] : T(0);
+      Fy[kk] = (ok && crow) ? Ft[plane + idx] : T(0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Rv[kk][q] = (ok && crow) ? rr[q * plane + idx] : T(0);
+    }
+    if (SHIFT) {
+      sE[0][j][lane] = ok ? eref[idx] : T(0);
+      sE[1][j][lane] = ok ? eref[plane + idx] : T(0);
+    }
+  }
+
+  // lane holding the reflection of this lane's first ghost column
+  int xm = lane;
+  if (!perx && x == -1) xm = lane + 1;
+  if (!perx && x == nx) xm = lane - 1;
+  const bool ywall_lo = !pery && y0 - 4 < 0, ywall_hi = !pery && y0 + TY + 4 > ny;
+
+  const T gam = k.gamma, omg = T(1) - k.gamma;
+  const int lm = clampi(lane - 1, 0, kWave - 1), lp = clampi(lane + 1, 0, kWave - 1);
+  double acc_r = 0.0, acc_g = 0.0;
+
+#pragma unroll
+  for (int app = 0; app < 2; ++app) {
+    const int e = 2 * app;  // rows / lanes [e, RR - e) hold a valid iterate
+    // ---- D(g)
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int j = w + 4 * kk;
+      T dv = k.kD * el_ms(G[kk]);
+      if (app == 1) dv = __shfl(dv, xm, kWave);
+      if (j >= e && j < RR - e) sD[j][lane] = dv;
+    }
+    if (app == 1 && (ywall_lo || ywall_hi)) {
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) {
+        const int j = w + 4 * kk;
+        const int y = y0 - 4 + j;
+        if (ywall_lo && y == -1) sD[j][lane] = sD[j + 1][lane];
+        if (ywall_hi && y == ny) sD[j][lane] = sD[j - 1][lane];
+      }
+    }
+    __syncthreads();
+    // ---- self-force and collision
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int j = w + 4 * kk;
+      if (j >= e + 1 && j < RR - e - 1) {
+        T v[3][3] = {{sD[j - 1][lm], sD[j - 1][lane], sD[j - 1][lp]},
+                     {sD[j][lm], sD[j][lane], sD[j][lp]},
+                     {sD[j + 1][lm], sD[j + 1][lane], sD[j + 1][lp]}};
+        T gx_, gy_;
+        grad_c(v, gx_, gy_);
+        T u[8], s8[8];
+        T fx = k.cstar * gx_, fy = k.cstar * gy_;
+        if (FINE) {
+          fx += Fx[kk];
+          fy += Fy[kk];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) u[q] = G[kk][q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) u[q] = G[kk][q] - Rv[kk][q];
+        }
+        el_collide(u, fx, fy, k, s8);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sS[q][j - 1][lane] = s8[q];
+      }
+    }
+    __syncthreads();
+    // ---- pull-stream with the boundary rules, under-relaxation
+    const bool pl = lane >= e + 2 && lane < kWave - e - 2;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int j = w + 4 * kk;
+      if (j < e + 2 || j >= RR - e - 2) continue;  // wave-uniform
+      const int y = y0 - 4 + j;
+      const bool yreal = pery ? (y >= -4 && y < ny + 4) : (y >= 0 && y < ny);
+      const bool real = pl && xreal && yreal;
+      const int gy = ghost_map(clampi(y, -4, ny + 3), ny, pery);
+      const int c = j - 1;
+      const int lc = pl ? lane : 4;  // keep LDS indices in range on idle lanes
+      T gi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
+      T ex = T(0), ey = T(0);
+      if (SHIFT) {
+        ex = sE[0][j][lc];
+        ey = sE[1][j][lc];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          gi[q] += el_geq<T>(q, sE[0][j - cy8(q)][lc - cx8(q)] - ex, sE[1][j - cy8(q)][lc - cx8(q)] - ey);
+      }
+      const bool wl = real && !perx && x == 0, wr = real && !perx && x == nx - 1;
+      const bool wb = real && !pery && y == 0, wt = real && !pery && y == ny - 1;
+      if (wl || wr || wb || wt) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int cx = cx8(q), cy = cy8(q);
+          const bool ox = (cx > 0 && wl) || (cx < 0 && wr);
+          const bool oy = (cy > 0 && wb) || (cy < 0 && wt);
+          if (!(ox || oy)) continue;
+          const int elx = cx > 0 ? P.el[kLeft] : P.el[kRight];
+          const int ely = cy > 0 ? P.el[kBottom] : P.el[kTop];
+          T v = T(0);
+          bool usex = false, half = false;
+          if (ox && oy) {
+            if (elx == kElSymmetry && ely == kElSymmetry) {
+              v = sS[opp8(q)][c][lc];
+              if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+            } else {
+              usex = ely == kElSymmetry;
+              half = true;
+            }
+          } else if (ox) {
+            usex = true;
+            if (elx == kElSymmetry) {
+              v = sS[mx8(q)][c - cy][lc];
+              if (SHIFT) v += el_geq<T>(mx8(q), sE[0][j - cy][lc], sE[1][j - cy][lc]) - el_geq<T>(q, ex, ey);
+            } else {
+              half = true;
+            }
+          } else {
+            if (ely == kElSymmetry) {
+              v = sS[my8(q)][c][lc - cx];
+              if (SHIFT) v += el_geq<T>(my8(q), sE[0][j][lc - cx], sE[1][j][lc - cx]) - el_geq<T>(q, ex, ey);
+            } else {
+              half = true;
+            }
+          }
+          if (half) {
+            const int type = usex ? elx : ely;
+            const double* bc = FINE ? (usex ? (cx > 0 ? P.elbc[kLeft] : P.elbc[kRight])
+                                            : (cy > 0 ? P.elbc[kBottom] : P.elbc[kTop]))
+                                    : nullptr;
+            const int bidx = usex ? gy : gx;
+            const T add = bc ? T(bc[8 * bidx + q]) : T(0);
+            const T o = sS[opp8(q)][c][lc];
+            if (type == kElDirichlet) {
+              v = o + add;
+              if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+            } else {
+              v = -o + add;
+            }
+          }
+          gi[q] = v;
+        }
+      }
+      if (app == 1) {
+        const bool out = pl && x >= 0 && x < nx && y < ny && lane >= 4 && lane < kWave - 4;
+        if (a.partials && out) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const double rho = double(G[kk][q]) - double(gi[q]);
+            double gf = double(G[kk][q]);
+            if (SHIFT) gf += double(el_geq<T>(q, ex, ey));
+            acc_r += rho * rho;
+            acc_g += gf * gf;
+          }
+        }
+        if (out) {
+          const int64_t oidx = (int64_t)y * pitch + x;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = omg * G[kk][q] + gam * gi[q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gam * gi[q];
+      }
+    }
+  }
+  if (a.partials) {
+    acc_r = wave_sum(acc_r);
+    acc_g = wave_sum(acc_g);
+    if (lane == 0) {
+      sRed[2 * w] = acc_r;
+      sRed[2 * w + 1] = acc_g;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      P.partials2[2 * te.y] = (sRed[0] + sRed[2]) + (sRed[4] + sRed[6]);
+      P.partials2[2 * te.y + 1] = (sRed[1] + sRed[3]) + (sRed[5] + sRed[7]);
+    }
+  }
+}
+
+template <typename T, typename Tc, bool FINE, bool SHIFT>
+hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT>), dim3(ntiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ======================================================================
 // flow step: D^n, centred coupling source (eq. source:implicit), pressure
 // (eq. pressure), SRT collision with source (eqs. pressure:collision,
 // pressure:collision:source), pull-stream and boundary rules
@@ -985,9 +1255,11 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
   const ProbD& P = a.probs[a.pids[blockIdx.x]];
   __shared__ double sr[256], sg[256];
   double r = 0.0, g = 0.0;
-  for (int k = threadIdx.x; k < P.ntiles_fine; k += 256) {
-    r += P.partials[2 * k];
-    g += P.partials[2 * k + 1];
+  const int n = a.fused ? P.ntiles_fine2 : P.ntiles_fine;
+  const double* part = a.fused ? P.partials2 : P.partials;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    r += part[2 * k];
+    g += part[2 * k + 1];
   }
   sr[threadIdx.x] = r;
   sg[threadIdx.x] = g;
@@ -1062,6 +1334,15 @@ BIOT_SWEEP(float, float)
 BIOT_SWEEP(float, double)
 BIOT_SWEEP(double, double)
 #undef BIOT_SWEEP
+template hipError_t launch_tsweep2<float, float, true, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, false, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, false, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, true, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, true, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, false, false>(const SweepL&, int, hipStream_t);
 
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<float, true>(const CellL&, int, hipStream_t);
