@@ -193,7 +193,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
   lo.tail_depth = tail_depth_of(lo);
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
-  lo.ntiles_fine2 = sweep2_tiles(p->nx, p->ny, lo.fdbl);
+  lo.ntiles_fine2 = sweepn_tiles(p->nx, p->ny, lo.fdbl, 2);
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
   for (int s = 0; s < 4; ++s) {
@@ -214,7 +214,8 @@ void make_layout(const bp_problem* p, Layout& lo) {
 size_t tile_entries_for(const Layout& lo) {
   size_t t = 1;
   for (int l = 1; l <= lo.L; ++l)
-    t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4 + sweep2_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl);
+    t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4 + sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 2) +
+         sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 4);
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
   return t;
@@ -413,7 +414,8 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.lv[l].ny = v.ny;
     d.lv[l].pitch = v.pitch;
     d.lv[l].tiles_x = sweep_tiles_x(v.nx);
-    d.lv[l].tiles_x2 = sweep2_tiles_x(v.nx);
+    d.lv[l].tiles_x2 = sweepn_tiles_x(v.nx, 2);
+    d.lv[l].tiles_x4 = sweepn_tiles_x(v.nx, 4);
     d.lv[l].dbl = v.dbl ? 1 : 0;
     d.lv[l].plane = v.plane;
   }
@@ -493,7 +495,7 @@ enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_A
 struct Op {
   OpKind kind;
   int mode = 0;           // sweep mode
-  bool fused = false;     // two smoothing applications per launch
+  int apps = 1;           // smoothing applications per launch
   int tdbl = 0, cdbl = 0; // sweep storage types (level, coarser level)
   bool shift = false;
   SweepL sw{};
@@ -508,11 +510,16 @@ struct Op {
 // set 0: full set of the time-step schedule (problems not inside their coarse
 // tail at this depth), set 1: its restriction set (problems with a coarser
 // level), sets 2 and 3: the same without the tail (inspection operations),
-// set 4: set 0 in the tiles of the two-application sweep
-constexpr int kSetFused = 4;
+// sets 4 and 5: set 0 in the tiles of the two- and four-application sweeps
+constexpr int kSetFused = 4, kSetQuad = 5;
+// a coarse depth whose launches cover at most this many cells in all take four
+// applications per launch: such launches are latency-bound, and the wider halo
+// costs little there
+constexpr int64_t kQuadMaxCells = 256 * 256;
 struct DepthLists {
-  int off[5][3] = {};
-  int cnt[5][3] = {};
+  int off[6][3] = {};
+  int cnt[6][3] = {};
+  bool quad = false;  // the depth's schedule set is small in all
   int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
@@ -537,6 +544,7 @@ struct Engine {
   bool graph_valid = false, use_graph = true;
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
+  bool quad = true;  // four-application sweeps on small coarse levels
   double* host_pin = nullptr;
 };
 
@@ -576,7 +584,7 @@ bp_status engine_upload(Engine& E) {
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
-    for (int set = 0; set < 5; ++set)
+    for (int set = 0; set < 6; ++set)
       for (int g = 0; g < 3; ++g) {
         E.depth[d].off[set][g] = (int)tiles.size();
         for (size_t i = 0; i < np; ++i) {
@@ -584,14 +592,23 @@ bp_status engine_upload(Engine& E) {
           const int l = P.L - d;
           const int td = P.lo.tail_depth;
           if (l < 1 || (set < 4 && (set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
-          if ((set < 2 || set == kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
+          if ((set < 2 || set >= kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
           const LevelLay& v = P.lo.lv[l];
-          const int nt = set == kSetFused ? sweep2_tiles(v.nx, v.ny, v.dbl) : sweep_tiles(v.nx, v.ny);
+          const int nt = set == kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, 2)
+                         : set == kSetQuad ? sweepn_tiles(v.nx, v.ny, v.dbl, 4)
+                                           : sweep_tiles(v.nx, v.ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
         if (E.xcd_order) xcd_order(tiles, E.depth[d].off[set][g]);
         E.depth[d].cnt[set][g] = (int)tiles.size() - E.depth[d].off[set][g];
       }
+    int64_t depth_cells = 0;
+    for (size_t i = 0; i < np; ++i) {
+      const Prob& P = *E.probs[i];
+      const int l = P.L - d, td = P.lo.tail_depth;
+      if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
+    }
+    E.depth[d].quad = E.quad && d > 0 && depth_cells <= kQuadMaxCells;
     E.depth[d].tail_off = (int)tiles.size();
     for (size_t i = 0; i < np; ++i)
       if (E.probs[i]->lo.tail_depth == d && d > 0) tiles.push_back(make_int2((int)i, 0));
@@ -641,7 +658,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     if (cnt == 0) continue;
     Op o;
     o.kind = OP_SWEEP;
-    o.fused = set == kSetFused;
+    o.apps = set == kSetFused ? 2 : (set == kSetQuad ? 4 : 1);
     o.mode = mode;
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
@@ -659,20 +676,21 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
 }
 
 // `count` smoothing applications at depth d, ping-ponging from buffer `sel`:
-// with fusion, pairs of applications run in one two-application launch, a
-// single launch takes an odd remainder first.  Only the first launch may read
-// a zero input or add the coarse correction, only the last writes the norm
-// partials.  Returns the buffer holding the result.
+// with fusion, four (small coarse levels) or two applications run in one
+// launch, a single launch takes an odd remainder first.  Only the first launch
+// may read a zero input or add the coarse correction, only the last writes the
+// norm partials.  Returns the buffer holding the result.
 int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, int sel, bool zero_in, bool prolong,
                   bool partials, bool fuse) {
   bool first = true;
+  const bool quad = fuse && E.depth[d].quad;
   while (count > 0) {
-    const bool pair = fuse && count >= 2 && (count % 2 == 0);
+    const int apps = (quad && count % 4 == 0) ? 4 : ((fuse && count % 2 == 0) ? 2 : 1);
     const int in = (first && zero_in) ? 2 : sel;
     const int pro = (first && prolong) ? 1 : 0;
-    count -= pair ? 2 : 1;
+    count -= apps;
     const int part = (partials && count == 0) ? 1 : 0;
-    add_sweeps(E, ops, d, pair ? kSetFused : set, kSmooth, in, 1 - sel, pro, part);
+    add_sweeps(E, ops, d, apps == 4 ? kSetQuad : (apps == 2 ? kSetFused : set), kSmooth, in, 1 - sel, pro, part);
     sel = 1 - sel;
     first = false;
   }
@@ -763,10 +781,11 @@ void build_step_ops(Engine& E) {
 
 template <typename T, typename Tc>
 hipError_t sweep_launch(const Op& o, hipStream_t s) {
-  if (o.fused) {
-    if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false>(o.sw, o.count, s);
-    return o.shift ? launch_tsweep2<T, Tc, true, true>(o.sw, o.count, s)
-                   : launch_tsweep2<T, Tc, true, false>(o.sw, o.count, s);
+  if (o.apps == 4) return launch_tsweep2<T, Tc, false, false, 4>(o.sw, o.count, s);  // coarse depths only
+  if (o.apps == 2) {
+    if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false, 2>(o.sw, o.count, s);
+    return o.shift ? launch_tsweep2<T, Tc, true, true, 2>(o.sw, o.count, s)
+                   : launch_tsweep2<T, Tc, true, false, 2>(o.sw, o.count, s);
   }
   if (o.shift) {
     switch (o.mode) {
@@ -857,6 +876,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_NO_QUAD")) E.quad = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
   return BP_OK;

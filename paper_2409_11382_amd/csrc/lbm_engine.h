@@ -27,7 +27,8 @@ struct LevelD {
   void* r;           // coarse right-hand side (8 planes), null on the finest level
   int nx, ny, pitch;
   int tiles_x;       // sweep tiles along x: ceil(nx / kTileX)
-  int tiles_x2;      // two-application sweep tiles along x: ceil(nx / kTile2X)
+  int tiles_x2;      // two-application sweep tiles along x
+  int tiles_x4;      // four-application sweep tiles along x
   int dbl;           // FP64 storage
   int64_t plane;
 };
@@ -101,11 +102,24 @@ struct TailL {
 
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
-// two smoothing applications per launch: 56 x (4 NK - 8) output tiles
-constexpr int kTile2X = kWave - 8;
-constexpr int kNK2F32 = 5;   // 12 output rows in FP32 storage
-constexpr int kNK2F64 = 4;   // 8 output rows in FP64 storage
-template <typename T, typename Tc, bool FINE, bool SHIFT>
+// APPS = 2 or 4 smoothing applications per launch: tiles of
+// (64 - 4 APPS) x (WAVES NK - 4 APPS) outputs, NK rows per wave.  Pairs (used
+// on large levels, bandwidth-bound) take 4 waves of 5 (FP32) or 4 (FP64) rows;
+// quads (small coarse levels, latency-bound) take 16 waves of 2 rows, which
+// keeps each wave's chain of dependent work short.
+template <int APPS>
+__host__ __device__ constexpr int sweepn_waves() { return APPS == 2 ? 4 : 16; }
+template <typename T, int APPS>
+__host__ __device__ constexpr int sweepn_rows() {
+  return APPS == 2 ? (sizeof(T) == 8 ? 4 : 5) : 2;
+}
+inline int sweepn_tile_x(int apps) { return kWave - 4 * apps; }
+inline int sweepn_tile_y(int apps, bool dbl) {
+  const int rr = apps == 2 ? sweepn_waves<2>() * (dbl ? sweepn_rows<double, 2>() : sweepn_rows<float, 2>())
+                           : sweepn_waves<4>() * (dbl ? sweepn_rows<double, 4>() : sweepn_rows<float, 4>());
+  return rr - 4 * apps;
+}
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
@@ -126,10 +140,10 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 
 inline int sweep_tiles_x(int nx) { return (nx + kTileX - 1) / kTileX; }
 inline int sweep_tiles(int nx, int ny) { return sweep_tiles_x(nx) * ((ny + kTileY - 1) / kTileY); }
-inline int sweep2_tiles_x(int nx) { return (nx + kTile2X - 1) / kTile2X; }
-inline int sweep2_tiles(int nx, int ny, bool dbl) {
-  const int ty = 4 * (dbl ? kNK2F64 : kNK2F32) - 8;
-  return sweep2_tiles_x(nx) * ((ny + ty - 1) / ty);
+inline int sweepn_tiles_x(int nx, int apps) { return (nx + sweepn_tile_x(apps) - 1) / sweepn_tile_x(apps); }
+inline int sweepn_tiles(int nx, int ny, bool dbl, int apps) {
+  const int ty = sweepn_tile_y(apps, dbl);
+  return sweepn_tiles_x(nx, apps) * ((ny + ty - 1) / ty);
 }
 inline int cell_blocks(int nx, int ny) { return ((nx + kCellBX - 1) / kCellBX) * ((ny + kCellBY - 1) / kCellBY); }
 

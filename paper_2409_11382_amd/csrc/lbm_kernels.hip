@@ -287,26 +287,28 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 }
 
 // ======================================================================
-// two smoothing applications in one launch
+// several smoothing applications in one launch
 // ======================================================================
-// Same arithmetic as two k_tsweep smoothing launches.  The tile loads a
-// 64-column region with a halo of 4 (56 output columns, TY = 4 NK - 8 output
-// rows); each wave keeps its NK rows in registers across both applications,
-// whose valid region shrinks by 2 per application (D and collision need one
-// neighbour, the pull one more).  Between the applications only the first
-// ghost row/column of D must be restored by reflection (the loaded ghosts were
-// reflected copies; after the first application they hold unused values):
-// columns by a lane permutation, rows through LDS.  The intermediate iterate
-// of real cells outside the domain's periodic wrap is never needed.
-template <typename T, typename Tc, bool FINE, bool SHIFT>
-__global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
-  constexpr int NK = sizeof(T) == 8 ? kNK2F64 : kNK2F32;
-  constexpr int RR = 4 * NK;     // region rows (four halo rows each side)
-  constexpr int TY = RR - 8;     // output rows
+// Same arithmetic as APPS k_tsweep smoothing launches.  The tile loads a
+// 64-column region with a halo of H = 2 APPS (64 - 2H output columns,
+// TY = 4 NK - 2H output rows); each wave keeps its NK rows in registers across
+// the applications, whose valid region shrinks by 2 per application (D and
+// collision need one neighbour, the pull one more).  Between applications only
+// the first ghost row/column of D must be restored by reflection (the loaded
+// ghosts were reflected copies; after an application they hold unused
+// values): columns by a lane permutation, rows through LDS.
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
+__global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL a) {
+  constexpr int NW = sweepn_waves<APPS>();
+  constexpr int NK = sweepn_rows<T, APPS>();
+  constexpr int H = 2 * APPS;    // halo
+  constexpr int RR = NW * NK;    // region rows
+  constexpr int TY = RR - 2 * H; // output rows
+  constexpr int TXO = kWave - 2 * H;
   __shared__ T sD[RR][kWave];
   __shared__ T sS[8][RR - 2][kWave];
   __shared__ T sE[SHIFT ? 2 : 1][SHIFT ? RR : 1][kWave];
-  __shared__ double sRed[8];
+  __shared__ double sRed[2 * NW];
 
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
@@ -314,14 +316,15 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
   const LevelD& V = P.lv[l];
   const int nx = V.nx, ny = V.ny, pitch = V.pitch;
   const int64_t plane = V.plane;
-  const int tx = te.y % V.tiles_x2, ty = te.y / V.tiles_x2;
+  const int tiles_x = APPS == 2 ? V.tiles_x2 : V.tiles_x4;
+  const int tx = te.y % tiles_x, ty = te.y / tiles_x;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int x = tx * kTile2X - 4 + lane;
+  const int x = tx * TXO - H + lane;
   const int y0 = ty * TY;
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
   // a single reflection covers ghosts up to nx cells out; farther ones (levels
   // narrower than the halo) never reach a real cell and stay zero
-  const bool col_ok = x >= -4 && x < nx + 4 && (perx || (x >= -nx && x < 2 * nx));
+  const bool col_ok = x >= -H && x < nx + H && (perx || (x >= -nx && x < 2 * nx));
   const int gx = col_ok ? ghost_map(x, nx, perx) : 0;
   const bool xreal = col_ok && (perx || (x >= 0 && x < nx));
   const T* gin = a.in_sel == 2 ? nullptr : (const T*)(a.in_sel ? V.gB : V.gA);
@@ -348,9 +351,9 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
   // ---- load the region (ghosts as reflected or periodic copies)
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {
-    const int j = w + 4 * kk;
-    const int y = y0 - 4 + j;
-    const bool ok = col_ok && y >= -4 && y < ny + 4 && (pery || (y >= -ny && y < 2 * ny));
+    const int j = w + NW * kk;
+    const int y = y0 - H + j;
+    const bool ok = col_ok && y >= -H && y < ny + H && (pery || (y >= -ny && y < 2 * ny));
     const int gy = ok ? ghost_map(y, ny, pery) : 0;
     const int64_t idx = (int64_t)gy * pitch + gx;
 #pragma unroll
@@ -378,29 +381,29 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
   int xm = lane;
   if (!perx && x == -1) xm = lane + 1;
   if (!perx && x == nx) xm = lane - 1;
-  const bool ywall_lo = !pery && y0 - 4 < 0, ywall_hi = !pery && y0 + TY + 4 > ny;
+  const bool ywall_lo = !pery && y0 - H < 0, ywall_hi = !pery && y0 + TY + H > ny;
 
   const T gam = k.gamma, omg = T(1) - k.gamma;
   const int lm = clampi(lane - 1, 0, kWave - 1), lp = clampi(lane + 1, 0, kWave - 1);
   double acc_r = 0.0, acc_g = 0.0;
 
 #pragma unroll
-  for (int app = 0; app < 2; ++app) {
+  for (int app = 0; app < APPS; ++app) {
     const int e = 2 * app;  // rows / lanes [e, RR - e) hold a valid iterate
     // ---- D(g)
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + 4 * kk;
+      const int j = w + NW * kk;
       T dv = k.kD * el_ms(G[kk]);
-      if (app == 1) dv = __shfl(dv, xm, kWave);
+      if (app > 0) dv = __shfl(dv, xm, kWave);
       if (j >= e && j < RR - e) sD[j][lane] = dv;
     }
-    if (app == 1 && (ywall_lo || ywall_hi)) {
+    if (app > 0 && (ywall_lo || ywall_hi)) {
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
-        const int j = w + 4 * kk;
-        const int y = y0 - 4 + j;
+        const int j = w + NW * kk;
+        const int y = y0 - H + j;
         if (ywall_lo && y == -1) sD[j][lane] = sD[j + 1][lane];
         if (ywall_hi && y == ny) sD[j][lane] = sD[j - 1][lane];
       }
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
     // ---- self-force and collision
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + 4 * kk;
+      const int j = w + NW * kk;
       if (j >= e + 1 && j < RR - e - 1) {
         T v[3][3] = {{sD[j - 1][lm], sD[j - 1][lane], sD[j - 1][lp]},
                      {sD[j][lm], sD[j][lane], sD[j][lp]},
@@ -437,12 +440,12 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
     const bool pl = lane >= e + 2 && lane < kWave - e - 2;
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + 4 * kk;
+      const int j = w + NW * kk;
       if (j < e + 2 || j >= RR - e - 2) continue;  // wave-uniform
-      const int y = y0 - 4 + j;
-      const bool yreal = pery ? (y >= -4 && y < ny + 4) : (y >= 0 && y < ny);
+      const int y = y0 - H + j;
+      const bool yreal = pery ? (y >= -H && y < ny + H) : (y >= 0 && y < ny);
       const bool real = pl && xreal && yreal;
-      const int gy = ghost_map(clampi(y, -4, ny + 3), ny, pery);
+      const int gy = ghost_map(clampi(y, -H, ny + H - 1), ny, pery);
       const int c = j - 1;
       const int lc = pl ? lane : 4;  // keep LDS indices in range on idle lanes
       T gi[8];
@@ -511,8 +514,8 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
           gi[q] = v;
         }
       }
-      if (app == 1) {
-        const bool out = pl && x >= 0 && x < nx && y < ny && lane >= 4 && lane < kWave - 4;
+      if (app == APPS - 1) {
+        const bool out = pl && x >= 0 && x < nx && y < ny && lane >= H && lane < kWave - H;
         if (a.partials && out) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -543,16 +546,22 @@ __global__ __launch_bounds__(256) void k_tsweep2(SweepL a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      P.partials2[2 * te.y] = (sRed[0] + sRed[2]) + (sRed[4] + sRed[6]);
-      P.partials2[2 * te.y + 1] = (sRed[1] + sRed[3]) + (sRed[5] + sRed[7]);
+      double r = 0.0, g = 0.0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        r += sRed[2 * v];
+        g += sRed[2 * v + 1];
+      }
+      P.partials2[2 * te.y] = r;
+      P.partials2[2 * te.y + 1] = g;
     }
   }
 }
 
-template <typename T, typename Tc, bool FINE, bool SHIFT>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT>), dim3(ntiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS>), dim3(ntiles), dim3(kWave * sweepn_waves<APPS>()), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1334,15 +1343,18 @@ BIOT_SWEEP(float, float)
 BIOT_SWEEP(float, double)
 BIOT_SWEEP(double, double)
 #undef BIOT_SWEEP
-template hipError_t launch_tsweep2<float, float, true, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, true, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, false, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, false, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, true, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, true, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, false, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, false, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, false, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, true, true, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, true, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, false, false, 2>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, false, false, 4>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, false, false, 4>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<double, double, false, false, 4>(const SweepL&, int, hipStream_t);
 
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<float, true>(const CellL&, int, hipStream_t);
