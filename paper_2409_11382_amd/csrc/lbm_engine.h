@@ -103,15 +103,15 @@ struct TailL {
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
 // APPS = 2 or 4 smoothing applications per launch: tiles of
-// (64 - 4 APPS) x (WAVES NK - 4 APPS) outputs, NK rows per wave.  Pairs (used
-// on large levels, bandwidth-bound) take 4 waves of 5 (FP32) or 4 (FP64) rows;
-// quads (small coarse levels, latency-bound) take 16 waves of 2 rows, which
-// keeps each wave's chain of dependent work short.
+// (64 - 4 APPS) x (WAVES NK - 4 APPS) outputs, NK rows per wave.  Pairs take
+// 8 waves of 3 (FP32) or 2 (FP64) rows, quads (small coarse levels) 16 waves
+// of 2 rows: few rows per wave keep each wave's chain of dependent work short,
+// which is what bounds the smaller grids.
 template <int APPS>
-__host__ __device__ constexpr int sweepn_waves() { return APPS == 2 ? 4 : 16; }
+__host__ __device__ constexpr int sweepn_waves() { return APPS == 2 ? 8 : 16; }
 template <typename T, int APPS>
 __host__ __device__ constexpr int sweepn_rows() {
-  return APPS == 2 ? (sizeof(T) == 8 ? 4 : 5) : 2;
+  return APPS == 2 ? (sizeof(T) == 8 ? 2 : 3) : 2;
 }
 inline int sweepn_tile_x(int apps) { return kWave - 4 * apps; }
 inline int sweepn_tile_y(int apps, bool dbl) {
