@@ -214,8 +214,10 @@ void make_layout(const bp_problem* p, Layout& lo) {
 size_t tile_entries_for(const Layout& lo) {
   size_t t = 1;
   for (int l = 1; l <= lo.L; ++l)
-    t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4 + sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 2) +
-         sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 4);
+  {
+    t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
+    for (int A = 2; A <= 5; ++A) t += (size_t)sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, A);
+  }
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
   return t;
@@ -414,8 +416,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.lv[l].ny = v.ny;
     d.lv[l].pitch = v.pitch;
     d.lv[l].tiles_x = sweep_tiles_x(v.nx);
-    d.lv[l].tiles_x2 = sweepn_tiles_x(v.nx, 2);
-    d.lv[l].tiles_x4 = sweepn_tiles_x(v.nx, 4);
+    for (int A = 2; A <= 5; ++A) d.lv[l].tiles_xn[A] = sweepn_tiles_x(v.nx, A);
     d.lv[l].dbl = v.dbl ? 1 : 0;
     d.lv[l].plane = v.plane;
   }
@@ -510,16 +511,30 @@ struct Op {
 // set 0: full set of the time-step schedule (problems not inside their coarse
 // tail at this depth), set 1: its restriction set (problems with a coarser
 // level), sets 2 and 3: the same without the tail (inspection operations),
-// sets 4 and 5: set 0 in the tiles of the two- and four-application sweeps
-constexpr int kSetFused = 4, kSetQuad = 5;
+// sets 4..7: set 0 in the tiles of the multi-application sweeps with 2, 4, 3
+// and 5 applications (the last two end with the residual and restriction)
+constexpr int kSetFused = 4, kSetQuad = 5, kSetFusedR = 6, kSetQuadR = 7;
+int set_apps(int set) {
+  switch (set) {
+    case kSetFused: return 2;
+    case kSetQuad: return 4;
+    case kSetFusedR: return 3;
+    case kSetQuadR: return 5;
+    default: return 1;
+  }
+}
+// depths whose launches cover at most this many cells in all are
+// latency-bound: there the restriction joins the last pre-smoothing launch
+constexpr int64_t kFuseResCells = 512 * 512;
 // a coarse depth whose launches cover at most this many cells in all take four
 // applications per launch: such launches are latency-bound, and the wider halo
 // costs little there
 constexpr int64_t kQuadMaxCells = 256 * 256;
 struct DepthLists {
-  int off[6][3] = {};
-  int cnt[6][3] = {};
-  bool quad = false;  // the depth's schedule set is small in all
+  int off[8][3] = {};
+  int cnt[8][3] = {};
+  bool quad = false;  // four applications per launch
+  bool fres = false;  // restriction fused into the last pre-smoothing launch
   int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
@@ -545,6 +560,7 @@ struct Engine {
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
+  bool fuse_res = true;  // restriction fused into pre-smoothing on latency-bound depths
   double* host_pin = nullptr;
 };
 
@@ -584,7 +600,7 @@ bp_status engine_upload(Engine& E) {
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
-    for (int set = 0; set < 6; ++set)
+    for (int set = 0; set < 8; ++set)
       for (int g = 0; g < 3; ++g) {
         E.depth[d].off[set][g] = (int)tiles.size();
         for (size_t i = 0; i < np; ++i) {
@@ -594,9 +610,7 @@ bp_status engine_upload(Engine& E) {
           if (l < 1 || (set < 4 && (set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
           if ((set < 2 || set >= kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
           const LevelLay& v = P.lo.lv[l];
-          const int nt = set == kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, 2)
-                         : set == kSetQuad ? sweepn_tiles(v.nx, v.ny, v.dbl, 4)
-                                           : sweep_tiles(v.nx, v.ny);
+          const int nt = set >= kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, set_apps(set)) : sweep_tiles(v.nx, v.ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
         if (E.xcd_order) xcd_order(tiles, E.depth[d].off[set][g]);
@@ -609,6 +623,7 @@ bp_status engine_upload(Engine& E) {
       if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
     }
     E.depth[d].quad = E.quad && d > 0 && depth_cells <= kQuadMaxCells;
+    E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
     E.depth[d].tail_off = (int)tiles.size();
     for (size_t i = 0; i < np; ++i)
       if (E.probs[i]->lo.tail_depth == d && d > 0) tiles.push_back(make_int2((int)i, 0));
@@ -658,7 +673,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     if (cnt == 0) continue;
     Op o;
     o.kind = OP_SWEEP;
-    o.apps = set == kSetFused ? 2 : (set == kSetQuad ? 4 : 1);
+    o.apps = set_apps(set);
     o.mode = mode;
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
@@ -679,18 +694,24 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
 // with fusion, four (small coarse levels) or two applications run in one
 // launch, a single launch takes an odd remainder first.  Only the first launch
 // may read a zero input or add the coarse correction, only the last writes the
-// norm partials.  Returns the buffer holding the result.
+// norm partials.  restrict_last: the last launch, if it is a multi-application
+// one, also restricts the residual of its result (*restricted tells).
+// Returns the buffer holding the result.
 int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, int sel, bool zero_in, bool prolong,
-                  bool partials, bool fuse) {
+                  bool partials, bool fuse, bool restrict_last = false, bool* restricted = nullptr) {
   bool first = true;
   const bool quad = fuse && E.depth[d].quad;
+  if (restricted) *restricted = false;
   while (count > 0) {
     const int apps = (quad && count % 4 == 0) ? 4 : ((fuse && count % 2 == 0) ? 2 : 1);
     const int in = (first && zero_in) ? 2 : sel;
     const int pro = (first && prolong) ? 1 : 0;
     count -= apps;
     const int part = (partials && count == 0) ? 1 : 0;
-    add_sweeps(E, ops, d, apps == 4 ? kSetQuad : (apps == 2 ? kSetFused : set), kSmooth, in, 1 - sel, pro, part);
+    const bool res = restrict_last && count == 0 && apps > 1;
+    const int s = apps == 4 ? (res ? kSetQuadR : kSetQuad) : (apps == 2 ? (res ? kSetFusedR : kSetFused) : set);
+    add_sweeps(E, ops, d, s, kSmooth, in, 1 - sel, pro, part);
+    if (res && restricted) *restricted = true;
     sel = 1 - sel;
     first = false;
   }
@@ -723,17 +744,18 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
   for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
   if (!here) return;
   fuse = fuse && tail && !first_done;
+  bool deeper = false;
+  for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   int sel = 0;
+  bool restricted = false;
   if (first_done) {
     // the first pre-smoothing application (A -> B) was issued separately
     sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, false);
   } else {
-    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0, false, false, fuse);
+    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0, false, false, fuse, deeper && E.depth[d].fres, &restricted);
   }
-  bool deeper = false;
-  for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   if (deeper) {
-    add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
+    if (!restricted) add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
     add_vcycle(E, ops, d + 1, false, false, tail, fuse);
   }
   add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse);
@@ -781,11 +803,19 @@ void build_step_ops(Engine& E) {
 
 template <typename T, typename Tc>
 hipError_t sweep_launch(const Op& o, hipStream_t s) {
-  if (o.apps == 4) return launch_tsweep2<T, Tc, false, false, 4>(o.sw, o.count, s);  // coarse depths only
-  if (o.apps == 2) {
-    if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false, 2>(o.sw, o.count, s);
-    return o.shift ? launch_tsweep2<T, Tc, true, true, 2>(o.sw, o.count, s)
-                   : launch_tsweep2<T, Tc, true, false, 2>(o.sw, o.count, s);
+  const bool fine = o.sw.depth == 0;
+  switch (o.apps) {
+    case 5: return launch_tsweep2<T, Tc, false, false, 4, true>(o.sw, o.count, s);  // coarse depths only
+    case 4: return launch_tsweep2<T, Tc, false, false, 4, false>(o.sw, o.count, s);
+    case 3:
+      if (!fine) return launch_tsweep2<T, Tc, false, false, 2, true>(o.sw, o.count, s);
+      return o.shift ? launch_tsweep2<T, Tc, true, true, 2, true>(o.sw, o.count, s)
+                     : launch_tsweep2<T, Tc, true, false, 2, true>(o.sw, o.count, s);
+    case 2:
+      if (!fine) return launch_tsweep2<T, Tc, false, false, 2, false>(o.sw, o.count, s);
+      return o.shift ? launch_tsweep2<T, Tc, true, true, 2, false>(o.sw, o.count, s)
+                     : launch_tsweep2<T, Tc, true, false, 2, false>(o.sw, o.count, s);
+    default: break;
   }
   if (o.shift) {
     switch (o.mode) {
@@ -877,6 +907,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_QUAD")) E.quad = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_NO_FUSE_RES")) E.fuse_res = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
   return BP_OK;

@@ -27,8 +27,7 @@ struct LevelD {
   void* r;           // coarse right-hand side (8 planes), null on the finest level
   int nx, ny, pitch;
   int tiles_x;       // sweep tiles along x: ceil(nx / kTileX)
-  int tiles_x2;      // two-application sweep tiles along x
-  int tiles_x4;      // four-application sweep tiles along x
+  int tiles_xn[6];   // multi-application sweep tiles along x, by applications per launch (2..5)
   int dbl;           // FP64 storage
   int64_t plane;
 };
@@ -102,24 +101,30 @@ struct TailL {
 
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
-// APPS = 2 or 4 smoothing applications per launch: tiles of
-// (64 - 4 APPS) x (WAVES NK - 4 APPS) outputs, NK rows per wave.  Pairs take
-// 8 waves of 3 (FP32) or 2 (FP64) rows, quads (small coarse levels) 16 waves
-// of 2 rows: few rows per wave keep each wave's chain of dependent work short,
-// which is what bounds the smaller grids.
-template <int APPS>
-__host__ __device__ constexpr int sweepn_waves() { return APPS == 2 ? 8 : 16; }
-template <typename T, int APPS>
+// Multi-application sweeps, by applications per launch A: 2 (a pair of
+// smoothing applications), 3 (a pair, then the residual of its result
+// restricted to the coarser level), 4 (four smoothing applications) and 5
+// (four, then the restricted residual).  A tile has (64 - 4 A) x
+// (WAVES NK - 4 A) outputs with NK rows per wave.  Few rows per wave keep each
+// wave's chain of dependent work short, which is what bounds the smaller grids.
+template <int A>
+__host__ __device__ constexpr int sweepn_waves() { return A <= 3 ? 8 : 16; }
+template <typename T, int A>
 __host__ __device__ constexpr int sweepn_rows() {
-  return APPS == 2 ? (sizeof(T) == 8 ? 2 : 3) : 2;
+  return A == 2 ? (sizeof(T) == 8 ? 2 : 3) : (A == 3 ? 3 : 2);
 }
-inline int sweepn_tile_x(int apps) { return kWave - 4 * apps; }
-inline int sweepn_tile_y(int apps, bool dbl) {
-  const int rr = apps == 2 ? sweepn_waves<2>() * (dbl ? sweepn_rows<double, 2>() : sweepn_rows<float, 2>())
-                           : sweepn_waves<4>() * (dbl ? sweepn_rows<double, 4>() : sweepn_rows<float, 4>());
-  return rr - 4 * apps;
+inline int sweepn_tile_x(int A) { return kWave - 4 * A; }
+inline int sweepn_tile_y(int A, bool dbl) {
+  int rr = 0;
+  switch (A) {
+    case 2: rr = sweepn_waves<2>() * (dbl ? sweepn_rows<double, 2>() : sweepn_rows<float, 2>()); break;
+    case 3: rr = sweepn_waves<3>() * sweepn_rows<float, 3>(); break;
+    case 4: rr = sweepn_waves<4>() * sweepn_rows<float, 4>(); break;
+    default: rr = sweepn_waves<5>() * sweepn_rows<float, 5>(); break;
+  }
+  return rr - 4 * A;
 }
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);

@@ -287,21 +287,23 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 }
 
 // ======================================================================
-// several smoothing applications in one launch
+// several applications in one launch
 // ======================================================================
-// Same arithmetic as APPS k_tsweep smoothing launches.  The tile loads a
-// 64-column region with a halo of H = 2 APPS (64 - 2H output columns,
-// TY = 4 NK - 2H output rows); each wave keeps its NK rows in registers across
-// the applications, whose valid region shrinks by 2 per application (D and
+// Same arithmetic as APPS k_tsweep smoothing launches, followed (RES) by the
+// residual/restriction launch on their result.  The tile loads a 64-column
+// region with a halo of H = 2 A, A = APPS + RES (64 - 2H output columns,
+// NW NK - 2H output rows); each wave keeps its NK rows in registers across the
+// applications, whose valid region shrinks by 2 per application (D and
 // collision need one neighbour, the pull one more).  Between applications only
 // the first ghost row/column of D must be restored by reflection (the loaded
 // ghosts were reflected copies; after an application they hold unused
 // values): columns by a lane permutation, rows through LDS.
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
-__global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL a) {
-  constexpr int NW = sweepn_waves<APPS>();
-  constexpr int NK = sweepn_rows<T, APPS>();
-  constexpr int H = 2 * APPS;    // halo
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
+__global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(SweepL a) {
+  constexpr int A = APPS + (RES ? 1 : 0);
+  constexpr int NW = sweepn_waves<A>();
+  constexpr int NK = sweepn_rows<T, A>();
+  constexpr int H = 2 * A;       // halo
   constexpr int RR = NW * NK;    // region rows
   constexpr int TY = RR - 2 * H; // output rows
   constexpr int TXO = kWave - 2 * H;
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
   const LevelD& V = P.lv[l];
   const int nx = V.nx, ny = V.ny, pitch = V.pitch;
   const int64_t plane = V.plane;
-  const int tiles_x = APPS == 2 ? V.tiles_x2 : V.tiles_x4;
+  const int tiles_x = V.tiles_xn[A];
   const int tx = te.y % tiles_x, ty = te.y / tiles_x;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int x = tx * TXO - H + lane;
@@ -335,6 +337,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
   const Tc* ec = pro ? (const Tc*)P.lv[l - 1].gA : nullptr;
   const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
   const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
+  Tc* rc = (RES && l > 1) ? (Tc*)P.lv[l - 1].r : nullptr;
   const T* eref = SHIFT ? (const T*)P.eref : nullptr;
   ElConst<T> k;
   k.om_s = T(P.om_s);
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
   double acc_r = 0.0, acc_g = 0.0;
 
 #pragma unroll
-  for (int app = 0; app < APPS; ++app) {
+  for (int app = 0; app < A; ++app) {
     const int e = 2 * app;  // rows / lanes [e, RR - e) hold a valid iterate
     // ---- D(g)
 #pragma unroll
@@ -514,8 +517,25 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
           gi[q] = v;
         }
       }
-      if (app == APPS - 1) {
-        const bool out = pl && x >= 0 && x < nx && y < ny && lane >= H && lane < kWave - H;
+      const bool out = pl && x >= 0 && x < nx && y >= 0 && y < ny && lane >= H && lane < kWave - H &&
+                       j >= H && j < RR - H;
+      if (RES && app == A - 1) {
+        // residual of the smoothed iterate, summed over lane pairs (x, x + 1);
+        // the row pairs are summed through LDS below
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const T rho = out ? G[kk][q] - gi[q] : T(0);
+          G[kk][q] = rho + from_right(rho);
+        }
+      } else if (RES && app == A - 2) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gam * gi[q];
+        if (out) {
+          const int64_t oidx = (int64_t)y * pitch + x;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = G[kk][q];
+        }
+      } else if (!RES && app == A - 1) {
         if (a.partials && out) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
@@ -534,6 +554,30 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
       } else {
 #pragma unroll
         for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gam * gi[q];
+      }
+    }
+  }
+  if (RES) {
+    // row pairs (y, y + 1) of the lane-pair sums, through LDS
+    __syncthreads();  // every pull has read sS
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int j = w + NW * kk;
+      if (j >= H && j < RR - H) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sS[q][j][lane] = G[kk][q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const int j = w + NW * kk;
+      const int y = y0 - H + j;
+      if (rc && j >= H && j < RR - H && (y & 1) == 0 && y < ny && lane >= H && lane < kWave - H && x >= 0 &&
+          x < nx && (x & 1) == 0) {
+        const int64_t cidx = (int64_t)(y >> 1) * cpitch + (x >> 1);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rc[q * cplane + cidx] = Tc(sS[q][j][lane] + sS[q][j + 1][lane]);
       }
     }
   }
@@ -558,10 +602,11 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS>()) void k_tsweep2(SweepL
   }
 }
 
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS>), dim3(ntiles), dim3(kWave * sweepn_waves<APPS>()), 0, s, a);
+  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES>), dim3(ntiles),
+                     dim3(kWave * sweepn_waves<APPS + (RES ? 1 : 0)>()), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1343,19 +1388,19 @@ BIOT_SWEEP(float, float)
 BIOT_SWEEP(float, double)
 BIOT_SWEEP(double, double)
 #undef BIOT_SWEEP
-template hipError_t launch_tsweep2<float, float, true, true, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, true, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, true, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, false, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, false, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, true, true, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, true, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, false, false, 2>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, false, false, 4>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, false, false, 4>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<double, double, false, false, 4>(const SweepL&, int, hipStream_t);
-
+#define BIOT_SWEEPN(T, Tc)                                                                            \
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, false>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, false>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, true>(const SweepL&, int, hipStream_t);    \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, true>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, false>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, true>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true>(const SweepL&, int, hipStream_t);
+BIOT_SWEEPN(float, float)
+BIOT_SWEEPN(float, double)
+BIOT_SWEEPN(double, double)
+#undef BIOT_SWEEPN
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<float, true>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<double, false>(const CellL&, int, hipStream_t);
