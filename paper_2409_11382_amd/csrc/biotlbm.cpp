@@ -847,7 +847,7 @@ hipError_t run_op(const Engine& E, const Op& o) {
     case OP_EXTRACT:
       if (E.fdbl) return E.shift ? launch_extract<double, true>(o.cl, o.count, s) : launch_extract<double, false>(o.cl, o.count, s);
       return E.shift ? launch_extract<float, true>(o.cl, o.count, s) : launch_extract<float, false>(o.cl, o.count, s);
-    case OP_TAIL: return launch_tail(o.tl, o.count, s);
+    case OP_TAIL: return launch_tail(o.tl, o.count, E.fdbl, s);
     case OP_FINALIZE: return launch_finalize(o.pl, o.count, s);
     case OP_ADVANCE: return launch_advance(o.pl, o.count, s);
   }

@@ -137,7 +137,8 @@ hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
 
-hipError_t launch_tail(const TailL& a, int nprobs, hipStream_t s);
+// levels >= 2 stored in FP64 (dbl) or FP32; level 1 is FP64 in both
+hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s);
 hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_advance(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

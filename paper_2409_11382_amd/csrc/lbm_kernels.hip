@@ -1142,162 +1142,187 @@ __device__ __forceinline__ void tail_tables(const ProbD& P, int nx, int ny, Tail
   }
 }
 
-template <typename T, int NC>
-__device__ __forceinline__ void tail_load(const LevelD& V, const void* buf, T (&A)[NC][8]) {
-  const int n = V.nx * V.ny;
-#pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4) {
-    const int c = threadIdx.x + kTailThreads * c4;
-    const int64_t idx = c < n ? (int64_t)(c / V.nx) * V.pitch + c % V.nx : 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) A[c4][q] = c < n ? ((const T*)buf)[q * V.plane + idx] : T(0);
-  }
-}
-
-template <typename T, int NC>
-__device__ __forceinline__ void tail_store(const LevelD& V, void* buf, const T (&A)[NC][8]) {
-  const int n = V.nx * V.ny;
-#pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4) {
-    const int c = threadIdx.x + kTailThreads * c4;
-    if (c >= n) continue;
-    const int64_t idx = (int64_t)(c / V.nx) * V.pitch + c % V.nx;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) ((T*)buf)[q * V.plane + idx] = A[c4][q];
-  }
-}
-
-// descent on level l: K pre-smoothing sweeps from zero, iterate to buffer A,
-// restricted residual (2 x 2 sums) to the right-hand side of level l - 1
-template <typename T, typename Tc>
-__device__ __forceinline__ void tail_descend(const ProbD& P, int l, int K, char* lds) {
-  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
-  const LevelD& V = P.lv[l];
-  const int nx = V.nx, ny = V.ny, n = nx * ny;
-  T* sD = (T*)lds;
-  T* sG = sD + n;
-  const ElConst<T> k = tail_consts<T>(P);
-  TailTab tb[NC];
-  tail_tables<NC>(P, nx, ny, tb);
-  T G[NC][8], R[NC][8];
-  tail_load<T, NC>(V, V.r, R);
-#pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
-  for (int s = 0; s < K; ++s) tail_relax<T, NC>(k, n, tb, G, R, sD, sG, true);
-  tail_store<T, NC>(V, V.gA, G);
-  tail_relax<T, NC>(k, n, tb, G, R, sD, sG, false);
-  __syncthreads();  // every pull has read sG
-#pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4) {
-    const int c = threadIdx.x + kTailThreads * c4;
-    if (c >= n) continue;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[c4][q];
-  }
-  __syncthreads();
-  const LevelD& C = P.lv[l - 1];
-  const int cnx = nx / 2, cn = cnx * (ny / 2);
-  Tc* rc = (Tc*)C.r;
-  for (int c = threadIdx.x; c < cn; c += kTailThreads) {
-    const int X = c % cnx, Y = c / cnx;
-    const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      rc[q * C.plane + (int64_t)Y * C.pitch + X] =
-          Tc((sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]));
-  }
-  __syncthreads();  // the right-hand side is complete before level l - 1 reads it
-}
-
-// coarsest level: 2K smoothing sweeps from zero, iterate to buffer A
+// one thread, one cell (c < n): the 8 planes of a level buffer
 template <typename T>
-__device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, char* lds) {
-  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
-  const LevelD& V = P.lv[1];
-  T* sD = (T*)lds;
-  T* sG = sD + V.nx * V.ny;
-  const ElConst<T> k = tail_consts<T>(P);
-  TailTab tb[NC];
-  tail_tables<NC>(P, V.nx, V.ny, tb);
-  T G[NC][8], R[NC][8];
-  tail_load<T, NC>(V, V.r, R);
+__device__ __forceinline__ void tail_load1(const LevelD& V, const void* buf, int c, T (&A)[1][8]) {
+  const bool in = c < V.nx * V.ny;
+  const int64_t idx = in ? (int64_t)(c / V.nx) * V.pitch + c % V.nx : 0;
 #pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) G[c4][q] = T(0);
-  for (int s = 0; s < 2 * K; ++s) tail_relax<T, NC>(k, V.nx * V.ny, tb, G, R, sD, sG, true);
-  tail_store<T, NC>(V, V.gA, G);
-  __syncthreads();
+  for (int q = 0; q < 8; ++q) A[0][q] = in ? ((const T*)buf)[q * V.plane + idx] : T(0);
 }
 
-// ascent on level l: iterate plus injected coarse correction, K
-// post-smoothing sweeps, iterate to buffer A
-template <typename T, typename Tc>
-__device__ __forceinline__ void tail_ascend(const ProbD& P, int l, int K, char* lds) {
-  constexpr int NC = sizeof(T) == 8 ? kTailCellsF64 / kTailThreads : kTailCellsF32 / kTailThreads;
-  const LevelD& V = P.lv[l];
-  const LevelD& C = P.lv[l - 1];
-  const int nx = V.nx, ny = V.ny, n = nx * ny;
-  T* sD = (T*)lds;
-  T* sG = sD + n;
-  const ElConst<T> k = tail_consts<T>(P);
-  T G[NC][8], R[NC][8];
-  tail_load<T, NC>(V, V.r, R);
-  tail_load<T, NC>(V, V.gA, G);
-  const Tc* ec = (const Tc*)C.gA;
+template <typename T>
+__device__ __forceinline__ void tail_store1(const LevelD& V, void* buf, int c, const T (&A)[1][8]) {
+  if (c >= V.nx * V.ny) return;
+  const int64_t idx = (int64_t)(c / V.nx) * V.pitch + c % V.nx;
 #pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4) {
-    const int c = threadIdx.x + kTailThreads * c4;
-    if (c >= n) continue;
-    const int64_t cidx = (int64_t)((c / nx) >> 1) * C.pitch + ((c % nx) >> 1);
+  for (int q = 0; q < 8; ++q) ((T*)buf)[q * V.plane + idx] = A[0][q];
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_zero(T (&A)[1][8]) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) G[c4][q] += T(ec[q * C.plane + cidx]);
+  for (int q = 0; q < 8; ++q) A[0][q] = T(0);
+}
+
+// Algorithm 4 on levels lt..1 of one problem; levels >= 2 are stored as T,
+// level 1 as T1.  Thread c owns cell c of every level.  Going down, the
+// restricted residual of a level stays in the registers of the thread that
+// owns the coarse cell (and is kept in the level's right-hand-side buffer for
+// the way up); going up, the coarse correction passes through LDS and each
+// level's stored iterate and right-hand side are fetched one level ahead.
+template <typename T, typename T1>
+__device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* lds) {
+  const int c = threadIdx.x;
+  T R[1][8], G[1][8];
+  T1 R1[1][8], G1[1][8];
+  if (lt >= 2)
+    tail_load1<T>(P.lv[lt], P.lv[lt].r, c, R);
+  else
+    tail_load1<T1>(P.lv[1], P.lv[1].r, c, R1);
+  // ---- descent: K pre-smoothing sweeps from zero, residual, restriction
+  for (int l = lt; l >= 2; --l) {
+    const LevelD& V = P.lv[l];
+    const int nx = V.nx, ny = V.ny, n = nx * ny;
+    T* sD = (T*)lds;
+    T* sG = sD + n;
+    const ElConst<T> k = tail_consts<T>(P);
+    TailTab tb[1];
+    tail_tables<1>(P, nx, ny, tb);
+    tail_zero(G);
+    for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
+    tail_store1<T>(V, V.gA, c, G);
+    tail_relax<T, 1>(k, n, tb, G, R, sD, sG, false);
+    __syncthreads();  // every pull has read sG
+    if (c < n) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
+    }
+    __syncthreads();
+    const LevelD& C = P.lv[l - 1];
+    const int cnx = nx / 2, cn = cnx * (ny / 2);
+    T sum[8];
+    if (c < cn) {
+      const int X = c % cnx, Y = c / cnx;
+      const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sum[q] = (sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sum[q] = T(0);
+    }
+    if (l - 1 >= 2) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) R[0][q] = sum[q];
+      tail_store1<T>(C, C.r, c, R);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) R1[0][q] = T1(sum[q]);
+      tail_store1<T1>(C, C.r, c, R1);
+    }
+    __syncthreads();  // sG is reused by the next level
   }
-  TailTab tb[NC];
-  tail_tables<NC>(P, nx, ny, tb);
-  for (int s = 0; s < K; ++s) tail_relax<T, NC>(k, n, tb, G, R, sD, sG, true);
-  tail_store<T, NC>(V, V.gA, G);
-  __syncthreads();
+  // prefetch level 2's stored iterate and right-hand side for the way up (in
+  // FP64 the registers are not there: those levels load when they start)
+  constexpr bool kPrefetch = sizeof(T) == 4;
+  T Gn[1][8], Rn[1][8];
+  if (kPrefetch && lt >= 2) {
+    tail_load1<T>(P.lv[2], P.lv[2].gA, c, Gn);
+    tail_load1<T>(P.lv[2], P.lv[2].r, c, Rn);
+  }
+  // ---- coarsest level: 2K smoothing sweeps from zero
+  {
+    const LevelD& V = P.lv[1];
+    const int n = V.nx * V.ny;
+    T1* sD = (T1*)lds;
+    T1* sG = sD + n;
+    const ElConst<T1> k = tail_consts<T1>(P);
+    TailTab tb[1];
+    tail_tables<1>(P, V.nx, V.ny, tb);
+    tail_zero(G1);
+    for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G1, R1, sD, sG, true);
+    tail_store1<T1>(V, V.gA, c, G1);
+    __syncthreads();  // every pull has read sG
+    if (c < n) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sG[q * n + c] = G1[0][q];
+    }
+    __syncthreads();
+  }
+  // ---- ascent: iterate plus injected coarse correction, K post-smoothing
+  // sweeps; the coarse level's result sits in LDS after its sD plane
+  for (int l = 2; l <= lt; ++l) {
+    const LevelD& V = P.lv[l];
+    const int nx = V.nx, ny = V.ny, n = nx * ny;
+    const int cn = (nx / 2) * (ny / 2);
+    if (kPrefetch) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        G[0][q] = Gn[0][q];
+        R[0][q] = Rn[0][q];
+      }
+    } else {
+      tail_load1<T>(V, V.gA, c, G);
+      tail_load1<T>(V, V.r, c, R);
+    }
+    if (c < n) {
+      const int ci = ((c / nx) >> 1) * (nx / 2) + ((c % nx) >> 1);
+      if (l == 2) {
+        const T1* ex = (const T1*)lds + cn;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) G[0][q] += T(ex[q * cn + ci]);
+      } else {
+        const T* ex = (const T*)lds + cn;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) G[0][q] += ex[q * cn + ci];
+      }
+    }
+    if (kPrefetch && l + 1 <= lt) {
+      tail_load1<T>(P.lv[l + 1], P.lv[l + 1].gA, c, Gn);
+      tail_load1<T>(P.lv[l + 1], P.lv[l + 1].r, c, Rn);
+    }
+    T* sD = (T*)lds;
+    T* sG = sD + n;
+    const ElConst<T> k = tail_consts<T>(P);
+    TailTab tb[1];
+    tail_tables<1>(P, nx, ny, tb);
+    for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
+    if (l == lt) {
+      tail_store1<T>(V, V.gA, c, G);
+    } else {
+      __syncthreads();  // every pull has read sG
+      if (c < n) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
+      }
+      __syncthreads();
+    }
+  }
 }
 
+template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
   extern __shared__ char lds[];
   const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
-  const int lt = P.L - a.depth;
-  for (int l = lt; l >= 2; --l) {
-    if (P.lv[l].dbl)
-      tail_descend<double, double>(P, l, a.K, lds);
-    else if (P.lv[l - 1].dbl)
-      tail_descend<float, double>(P, l, a.K, lds);
-    else
-      tail_descend<float, float>(P, l, a.K, lds);
-  }
-  if (P.lv[1].dbl)
-    tail_coarsest<double>(P, a.K, lds);
-  else
-    tail_coarsest<float>(P, a.K, lds);
-  for (int l = 2; l <= lt; ++l) {
-    if (P.lv[l].dbl)
-      tail_ascend<double, double>(P, l, a.K, lds);
-    else if (P.lv[l - 1].dbl)
-      tail_ascend<float, double>(P, l, a.K, lds);
-    else
-      tail_ascend<float, float>(P, l, a.K, lds);
-  }
+  tail_run<T, double>(P, P.L - a.depth, a.K, lds);
 }
 
-hipError_t launch_tail(const TailL& a, int nprobs, hipStream_t s) {
+hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
   if (nprobs <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tail, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kTailLdsBytes);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kTailLdsBytes);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL(k_tail, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  if (dbl)
+    hipLaunchKernelGGL(k_tail<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  else
+    hipLaunchKernelGGL(k_tail<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
   return hipGetLastError();
 }
 
