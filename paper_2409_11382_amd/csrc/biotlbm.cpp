@@ -129,7 +129,7 @@ struct Layout {
   bool fdbl = true, shift = false;
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
-  size_t off_eta, off_sig, off_part, off_part2, off_scal, off_elbc[4], off_ftype[4], off_flbc[4];
+  size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_elbc[4], off_ftype[4], off_flbc[4];
   int ntiles_fine = 0, ntiles_fine2 = 0;
   int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
   size_t total = 0;
@@ -196,6 +196,11 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.ntiles_fine2 = sweepn_tiles(p->nx, p->ny, lo.fdbl, 2);
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
+  // gather tables of the coarse tail's levels (8 words per cell, level 1 first)
+  size_t tcells = 0;
+  if (lo.tail_depth > 0)
+    for (int l = 1; l <= lo.L - lo.tail_depth; ++l) tcells += (size_t)lo.lv[l].nx * lo.lv[l].ny;
+  lo.off_ttab = take(tcells * 8 * sizeof(uint32_t));
   for (int s = 0; s < 4; ++s) {
     const int n = side_len(s, p->nx, p->ny);
     lo.off_elbc[s] = take((size_t)n * 8 * 8);
@@ -451,7 +456,15 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.phase = (int*)(base + lo.off_scal + 32);
   d.flags = (int*)(base + lo.off_scal + 40);
   d.ntiles_fine = lo.ntiles_fine;
+  d.ttab = (uint32_t*)(base + lo.off_ttab);
   HIPCHK(launch_fill_zero(base, lo.total, st));
+  if (lo.tail_depth > 0) {
+    size_t o = 0;
+    for (int l = 1; l <= lo.L - lo.tail_depth; ++l) {
+      HIPCHK(launch_tail_tables(d.el, lo.lv[l].nx, lo.lv[l].ny, d.ttab + o, st));
+      o += (size_t)8 * lo.lv[l].nx * lo.lv[l].ny;
+    }
+  }
 
   // permeability -> lattice relaxation rate of the flow LBM (eq. pressure:rate)
   const size_t N = (size_t)p->nx * p->ny;

@@ -60,6 +60,7 @@ struct ProbD {
   double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
   int ntiles_fine;            // sweep tiles of the finest level
   int ntiles_fine2;           // two-application sweep tiles of the finest level
+  uint32_t* ttab;             // coarse tail: per-cell gather tables of levels 1.. (8 words per cell)
 };
 
 struct SweepL {
@@ -139,6 +140,9 @@ hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
 
 // levels >= 2 stored in FP64 (dbl) or FP32; level 1 is FP64 in both
 hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s);
+// gather tables of one coarse-tail level (nx * ny <= kTailThreads) for the
+// elastic side types el[4]
+hipError_t launch_tail_tables(const int* el, int nx, int ny, uint32_t* out, hipStream_t s);
 hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_advance(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -1044,11 +1044,11 @@ struct TailTab {
   uint32_t dn[4], pl[4];
 };
 
-__device__ __forceinline__ TailTab tail_table(const ProbD& P, int c, int nx, int ny) {
+__device__ __forceinline__ TailTab tail_table(const int* el, int c, int nx, int ny) {
   TailTab tb;
   const int n = nx * ny;
   const int x = c % nx, y = c / nx;
-  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+  const bool perx = el[kLeft] == kElPeriodic, pery = el[kBottom] == kElPeriodic;
   uint32_t d[8];
   int k = 0;
 #pragma unroll
@@ -1059,7 +1059,7 @@ __device__ __forceinline__ TailTab tail_table(const ProbD& P, int c, int nx, int
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     tb.dn[j] = d[2 * j] | (d[2 * j + 1] << 16);
-    tb.pl[j] = tail_pull_code(2 * j, x, y, nx, ny, P.el, n) | (tail_pull_code(2 * j + 1, x, y, nx, ny, P.el, n) << 16);
+    tb.pl[j] = tail_pull_code(2 * j, x, y, nx, ny, el, n) | (tail_pull_code(2 * j + 1, x, y, nx, ny, el, n) << 16);
   }
   return tb;
 }
@@ -1133,13 +1133,43 @@ __device__ __forceinline__ void tail_relax(const ElConst<T>& k, int n, const Tai
   }
 }
 
-template <int NC>
-__device__ __forceinline__ void tail_tables(const ProbD& P, int nx, int ny, TailTab (&tb)[NC]) {
-#pragma unroll
-  for (int c4 = 0; c4 < NC; ++c4) {
-    const int c = threadIdx.x + kTailThreads * c4;
-    if (c < nx * ny) tb[c4] = tail_table(P, c, nx, ny);
+// the gather tables of level l (built once at setup by k_tail_tables)
+__device__ __forceinline__ const uint4* tail_tab_ptr(const ProbD& P, int l) {
+  size_t o = 0;
+  for (int m = 1; m < l; ++m) o += (size_t)P.lv[m].nx * P.lv[m].ny;
+  return (const uint4*)(P.ttab + 8 * o);
+}
+
+__device__ __forceinline__ void tail_tab_load(const ProbD& P, int l, int c, TailTab (&tb)[1]) {
+  if (c < P.lv[l].nx * P.lv[l].ny) {
+    const uint4* t = tail_tab_ptr(P, l) + 2 * c;
+    const uint4 a = t[0], b = t[1];
+    tb[0].dn[0] = a.x;
+    tb[0].dn[1] = a.y;
+    tb[0].dn[2] = a.z;
+    tb[0].dn[3] = a.w;
+    tb[0].pl[0] = b.x;
+    tb[0].pl[1] = b.y;
+    tb[0].pl[2] = b.z;
+    tb[0].pl[3] = b.w;
   }
+}
+
+__global__ __launch_bounds__(kTailThreads) void k_tail_tables(int4 el4, int nx, int ny, uint32_t* out) {
+  const int c = threadIdx.x;
+  if (c >= nx * ny) return;
+  const int el[4] = {el4.x, el4.y, el4.z, el4.w};
+  const TailTab tb = tail_table(el, c, nx, ny);
+  uint4* o = (uint4*)(out + 8 * c);
+  o[0] = make_uint4(tb.dn[0], tb.dn[1], tb.dn[2], tb.dn[3]);
+  o[1] = make_uint4(tb.pl[0], tb.pl[1], tb.pl[2], tb.pl[3]);
+}
+
+hipError_t launch_tail_tables(const int* el, int nx, int ny, uint32_t* out, hipStream_t s) {
+  if (nx * ny > kTailThreads) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tail_tables, dim3(1), dim3(kTailThreads), 0, s, make_int4(el[0], el[1], el[2], el[3]), nx, ny,
+                     out);
+  return hipGetLastError();
 }
 
 // one thread, one cell (c < n): the 8 planes of a level buffer
@@ -1188,7 +1218,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     T* sG = sD + n;
     const ElConst<T> k = tail_consts<T>(P);
     TailTab tb[1];
-    tail_tables<1>(P, nx, ny, tb);
+    tail_tab_load(P, l, c, tb);
     tail_zero(G);
     for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
     tail_store1<T>(V, V.gA, c, G);
@@ -1238,7 +1268,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     T1* sG = sD + n;
     const ElConst<T1> k = tail_consts<T1>(P);
     TailTab tb[1];
-    tail_tables<1>(P, V.nx, V.ny, tb);
+    tail_tab_load(P, 1, c, tb);
     tail_zero(G1);
     for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G1, R1, sD, sG, true);
     tail_store1<T1>(V, V.gA, c, G1);
@@ -1285,7 +1315,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     T* sG = sD + n;
     const ElConst<T> k = tail_consts<T>(P);
     TailTab tb[1];
-    tail_tables<1>(P, nx, ny, tb);
+    tail_tab_load(P, l, c, tb);
     for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
     if (l == lt) {
       tail_store1<T>(V, V.gA, c, G);
