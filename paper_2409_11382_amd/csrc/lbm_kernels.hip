@@ -1204,8 +1204,13 @@ __device__ __forceinline__ void tail_zero(T (&A)[1][8]) {
 template <typename T, typename T1>
 __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* lds) {
   const int c = threadIdx.x;
+  constexpr bool kPrefetch = sizeof(T) == 4;  // FP64 lacks the registers
   T R[1][8], G[1][8];
   T1 R1[1][8], G1[1][8];
+  // gather tables: tb for the level being swept, tn fetched one level ahead
+  // (order of use: lt, ..., 2, 1, 2, ..., lt)
+  TailTab tb[1], tn[1];
+  if (kPrefetch) tail_tab_load(P, lt, c, tn);
   if (lt >= 2)
     tail_load1<T>(P.lv[lt], P.lv[lt].r, c, R);
   else
@@ -1217,8 +1222,12 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     T* sD = (T*)lds;
     T* sG = sD + n;
     const ElConst<T> k = tail_consts<T>(P);
-    TailTab tb[1];
-    tail_tab_load(P, l, c, tb);
+    if (kPrefetch) {
+      tb[0] = tn[0];
+      tail_tab_load(P, l - 1, c, tn);
+    } else {
+      tail_tab_load(P, l, c, tb);
+    }
     tail_zero(G);
     for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
     tail_store1<T>(V, V.gA, c, G);
@@ -1254,7 +1263,6 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
   }
   // prefetch level 2's stored iterate and right-hand side for the way up (in
   // FP64 the registers are not there: those levels load when they start)
-  constexpr bool kPrefetch = sizeof(T) == 4;
   T Gn[1][8], Rn[1][8];
   if (kPrefetch && lt >= 2) {
     tail_load1<T>(P.lv[2], P.lv[2].gA, c, Gn);
@@ -1267,8 +1275,11 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     T1* sD = (T1*)lds;
     T1* sG = sD + n;
     const ElConst<T1> k = tail_consts<T1>(P);
-    TailTab tb[1];
-    tail_tab_load(P, 1, c, tb);
+    if (kPrefetch)
+      tb[0] = tn[0];
+    else
+      tail_tab_load(P, 1, c, tb);
+    if (kPrefetch && lt >= 2) tail_tab_load(P, 2, c, tn);
     tail_zero(G1);
     for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G1, R1, sD, sG, true);
     tail_store1<T1>(V, V.gA, c, G1);
@@ -1311,11 +1322,16 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
       tail_load1<T>(P.lv[l + 1], P.lv[l + 1].gA, c, Gn);
       tail_load1<T>(P.lv[l + 1], P.lv[l + 1].r, c, Rn);
     }
+    __syncthreads();  // the sweeps' sD overlaps the coarse result just read
     T* sD = (T*)lds;
     T* sG = sD + n;
     const ElConst<T> k = tail_consts<T>(P);
-    TailTab tb[1];
-    tail_tab_load(P, l, c, tb);
+    if (kPrefetch) {
+      tb[0] = tn[0];
+      if (l + 1 <= lt) tail_tab_load(P, l + 1, c, tn);
+    } else {
+      tail_tab_load(P, l, c, tb);
+    }
     for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
     if (l == lt) {
       tail_store1<T>(V, V.gA, c, G);
