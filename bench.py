@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # the kernel and the host code that orders its work lists (XCD-aware tile order)
 KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_device.h", "lbm_engine.h", "biotlbm.cpp")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fine_sweep_fp32_shifted_512.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fine_pair_sweep_fp32_shifted_512.txt")
 COPY_BYTES = 256 << 20
 
 
@@ -124,16 +124,19 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
 
 
 def dominant_kernel(solver, iters):
-    """The finest-level smoothing sweep: average device time of `iters`
-    back-to-back launches (one captured graph, HIP events on the solver's
-    stream) and its algorithmic bytes per launch."""
-    us, nbytes = solver.time_kernel(0, iters)
+    """The finest-level smoothing launch of the step: two applications per
+    launch (k_tsweep2<float,float,fine,shift,2,no-restriction>).  Average
+    device time of `iters` back-to-back launches (one captured graph, HIP
+    events on the solver's stream) and its algorithmic bytes per launch: the
+    populations read and written once, the explicit force and the displacement
+    reference read once, 4 B each (80 B per cell)."""
+    us, nbytes = solver.time_kernel(4, iters)
     achieved = nbytes / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_tsweep<float,float,smooth,shift> (finest-level smoothing sweep)",
-            "avg_us": round(us, 3), "bytes_per_launch": nbytes,
-            "bytes_per_cell": 80, "launches_timed": iters}
+            "kernel": "k_tsweep2<float,float,fine,shift,2 applications> (finest-level smoothing pair)",
+            "avg_us": round(us, 3), "bytes_per_launch": nbytes, "bytes_per_cell": 80,
+            "applications_per_launch": 2, "launches_timed": iters}
 
 
 def batched(steps, warmup, count=256):
