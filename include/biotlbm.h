@@ -157,8 +157,9 @@ bp_status bp_stats(const bp_solver *s, bp_run_stats *st);
 /* Average device time (microseconds, HIP events on the solver's stream) of
  * `iters` back-to-back launches of one kernel on the current state, replayed
  * as one captured graph: which = 0 finest-level smoothing sweep, 1 finest-level
- * residual/restriction, 2 flow step, 3 explicit force, 4 finest-level
- * two-application smoothing sweep.  *bytes receives the algorithmic HBM bytes
+ * residual/restriction, 2 flow step, 3 explicit force, 4 the finest level's
+ * multi-application smoothing launch of the time-step schedule (two or four
+ * applications).  *bytes receives the algorithmic HBM bytes
  * of one launch (each value the kernel must read or write, once).  The state
  * is left unchanged. */
 bp_status bp_time_kernel(bp_solver *s, int32_t which, int32_t iters, double *avg_us, double *bytes);

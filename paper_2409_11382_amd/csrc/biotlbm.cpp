@@ -193,7 +193,9 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
   lo.tail_depth = tail_depth_of(lo);
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
-  lo.ntiles_fine2 = sweepn_tiles(p->nx, p->ny, lo.fdbl, 2);
+  // partials of the multi-application sweeps: as many tiles as the pair or
+  // the quad geometry has, whichever the schedule uses on the finest level
+  lo.ntiles_fine2 = std::max(sweepn_tiles(p->nx, p->ny, lo.fdbl, 2), sweepn_tiles(p->nx, p->ny, lo.fdbl, 4));
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
   // gather tables of the coarse tail's levels (8 words per cell, level 1 first)
@@ -539,9 +541,10 @@ int set_apps(int set) {
 // depths whose launches cover at most this many cells in all are
 // latency-bound: there the restriction joins the last pre-smoothing launch
 constexpr int64_t kFuseResCells = 512 * 512;
-// a coarse depth whose launches cover at most this many cells in all take four
-// applications per launch: such launches are latency-bound, and the wider halo
-// costs little there
+// a depth whose launches cover at most this many cells in all takes four
+// applications per launch: its tiles (48 x 16 outputs, one 1024-thread block
+// per CU) fit one round over the 256 CUs, the launch is latency-bound and the
+// wider halo costs little there
 constexpr int64_t kQuadMaxCells = 256 * 256;
 struct DepthLists {
   int off[8][3] = {};
@@ -602,6 +605,10 @@ void xcd_order(std::vector<int2>& tiles, size_t off) {
   }
 }
 
+// four applications per launch at depth d (FP64 shifted storage has no LDS
+// room for them on the finest level)
+bool quad_at(const Engine& E, int d) { return E.depth[d].quad && !(d == 0 && E.fdbl && E.shift); }
+
 // write descriptors and tile lists for the current problem set
 bp_status engine_upload(Engine& E) {
   const size_t np = E.probs.size();
@@ -635,7 +642,7 @@ bp_status engine_upload(Engine& E) {
       const int l = P.L - d, td = P.lo.tail_depth;
       if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
     }
-    E.depth[d].quad = E.quad && d > 0 && depth_cells <= kQuadMaxCells;
+    E.depth[d].quad = E.quad && depth_cells <= kQuadMaxCells;
     E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
     E.depth[d].tail_off = (int)tiles.size();
     for (size_t i = 0; i < np; ++i)
@@ -666,6 +673,12 @@ bp_status engine_upload(Engine& E) {
   }
   E.init_cnt = (int)tiles.size() - E.init_off;
   if (tiles.size() > E.tiles_cap) return fail(BP_ERR_WORKSPACE, "tile lists exceed the engine area");
+  // norm partials of the finest level come from the launch geometry the
+  // schedule uses there
+  for (size_t i = 0; i < np; ++i) {
+    const Prob& P = *E.probs[i];
+    pd[i].ntiles_fine2 = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, quad_at(E, 0) ? 4 : 2);
+  }
   std::vector<int> pids(np);
   for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
   if (np) {
@@ -713,7 +726,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
 int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, int sel, bool zero_in, bool prolong,
                   bool partials, bool fuse, bool restrict_last = false, bool* restricted = nullptr) {
   bool first = true;
-  const bool quad = fuse && E.depth[d].quad;
+  const bool quad = fuse && quad_at(E, d);
   if (restricted) *restricted = false;
   while (count > 0) {
     const int apps = (quad && count % 4 == 0) ? 4 : ((fuse && count % 2 == 0) ? 2 : 1);
@@ -818,8 +831,14 @@ template <typename T, typename Tc>
 hipError_t sweep_launch(const Op& o, hipStream_t s) {
   const bool fine = o.sw.depth == 0;
   switch (o.apps) {
-    case 5: return launch_tsweep2<T, Tc, false, false, 4, true>(o.sw, o.count, s);  // coarse depths only
-    case 4: return launch_tsweep2<T, Tc, false, false, 4, false>(o.sw, o.count, s);
+    case 5:
+      if (!fine) return launch_tsweep2<T, Tc, false, false, 4, true>(o.sw, o.count, s);
+      return o.shift ? launch_tsweep2<T, Tc, true, true, 4, true>(o.sw, o.count, s)
+                     : launch_tsweep2<T, Tc, true, false, 4, true>(o.sw, o.count, s);
+    case 4:
+      if (!fine) return launch_tsweep2<T, Tc, false, false, 4, false>(o.sw, o.count, s);
+      return o.shift ? launch_tsweep2<T, Tc, true, true, 4, false>(o.sw, o.count, s)
+                     : launch_tsweep2<T, Tc, true, false, 4, false>(o.sw, o.count, s);
     case 3:
       if (!fine) return launch_tsweep2<T, Tc, false, false, 2, true>(o.sw, o.count, s);
       return o.shift ? launch_tsweep2<T, Tc, true, true, 2, true>(o.sw, o.count, s)
@@ -1445,7 +1464,7 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
   std::vector<Op> ops;
   switch (which) {
     case 0: add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 0); break;
-    case 4: add_sweeps(E, ops, 0, kSetFused, kSmooth, 0, 1, 0, 0); break;
+    case 4: add_sweeps(E, ops, 0, quad_at(E, 0) ? kSetQuad : kSetFused, kSmooth, 0, 1, 0, 0); break;
     case 1:
       if (P.L < 2) return fail(BP_ERR_ARG, "no coarser level");
       add_sweeps(E, ops, 0, 1, kRestrict, 0, 0, 0, 0);

@@ -1467,11 +1467,27 @@ BIOT_SWEEP(double, double)
   template hipError_t launch_tsweep2<T, Tc, false, false, 2, false>(const SweepL&, int, hipStream_t);  \
   template hipError_t launch_tsweep2<T, Tc, false, false, 2, true>(const SweepL&, int, hipStream_t);   \
   template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true>(const SweepL&, int, hipStream_t);
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true>(const SweepL&, int, hipStream_t);
 BIOT_SWEEPN(float, float)
 BIOT_SWEEPN(float, double)
 BIOT_SWEEPN(double, double)
 #undef BIOT_SWEEPN
+template hipError_t launch_tsweep2<float, float, true, true, 4, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 4, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, false>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, true>(const SweepL&, int, hipStream_t);
+// FP64 shifted storage has no LDS room for four applications; the schedule
+// never asks for them (these stubs keep the dispatch table complete)
+template <>
+hipError_t launch_tsweep2<double, double, true, true, 4, false>(const SweepL&, int, hipStream_t) {
+  return hipErrorInvalidConfiguration;
+}
+template <>
+hipError_t launch_tsweep2<double, double, true, true, 4, true>(const SweepL&, int, hipStream_t) {
+  return hipErrorInvalidConfiguration;
+}
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<float, true>(const CellL&, int, hipStream_t);
 template hipError_t launch_tflow<double, false>(const CellL&, int, hipStream_t);
