@@ -174,8 +174,11 @@ bp_status bp_destroy(bp_solver *s);
  * a time step covers the same multigrid depth of all problems (levels aligned
  * from the finest), so n problems cost about the launches of one.  Problems
  * must share the precision, K and the fixed number of V-cycles; grids,
- * parameters and boundary data may differ.  Results are bitwise identical to
- * solving each problem alone. */
+ * parameters and boundary data may differ.  Each problem's arithmetic is that
+ * of solving it alone; results are bitwise identical when the batch leaves the
+ * launch variants unchanged (a depth takes four-application launches or fuses
+ * the restriction according to the cells it covers in all), and otherwise
+ * agree to rounding (operations are fused differently in the variants). */
 typedef struct bp_batch bp_batch;
 bp_status bp_batch_workspace_bytes(const bp_problem *probs, int32_t n, size_t *device_bytes);
 bp_status bp_batch_create(const bp_problem *probs, int32_t n, void *device_ws, size_t ws_bytes,
@@ -196,7 +199,8 @@ bp_status bp_batch_destroy(bp_batch *b);
  * aligned from the finest, as in a batch; one captured graph per membership),
  * and finally retires requests that reached their step count: their fields
  * are copied to host memory held by the server and their pool memory is
- * released.  Results are bitwise identical to solving each request alone.
+ * released.  Results equal solving each request alone as in a batch (bitwise
+ * when the mix leaves the launch variants unchanged, else to rounding).
  * Requests must use the server's precision, K and fixed V-cycle count.
  * Calls on one server are not thread-safe; all device work runs on hip_stream.
  *

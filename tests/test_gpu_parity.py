@@ -272,7 +272,8 @@ def test_invalid_problems_rejected(lbm):
 @pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
 def test_batch_alone_equals_in_mix(lbm, prec):
     """Problems of different sizes, hierarchy depths, parameters and boundary
-    types advanced together give bitwise the same fields as each alone."""
+    types advanced together give bitwise the same fields as each alone (this
+    mix is small enough to keep every depth's launch variants)."""
     probs = [P.loaded_strip(n=64, alpha=0.7, kappa=0.3, ne_fixed=3),
              P.loaded_strip(n=128, nu=0.4, alpha=1.0, ne_fixed=3),
              mixed_walls(124, 68, seed=9).replace(ne_fixed=3, K=4),
