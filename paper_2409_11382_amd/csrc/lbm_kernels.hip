@@ -309,7 +309,9 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   constexpr int TXO = kWave - 2 * H;
   __shared__ T sD[RR][kWave];
   __shared__ T sS[8][RR - 2][kWave];
-  __shared__ T sE[SHIFT ? 2 : 1][SHIFT ? RR : 1][kWave];
+  // shifted storage: reference ex, ey and the sums ex + ey, ey - ex that the
+  // diagonal pulls' corrections need
+  __shared__ T sE[SHIFT ? 4 : 1][SHIFT ? RR : 1][kWave];
   __shared__ double sRed[2 * NW];
 
   const int2 te = a.tiles[blockIdx.x];
@@ -350,6 +352,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   T G[NK][8];
   T Rv[FINE ? 1 : NK][8];
   T Fx[FINE ? NK : 1], Fy[FINE ? NK : 1];
+  T Ex[SHIFT ? NK : 1], Ey[SHIFT ? NK : 1];  // own reference
 
   // ---- load the region (ghosts as reflected or periodic copies)
 #pragma unroll
@@ -375,8 +378,12 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
       for (int q = 0; q < 8; ++q) Rv[kk][q] = (ok && crow) ? rr[q * plane + idx] : T(0);
     }
     if (SHIFT) {
-      sE[0][j][lane] = ok ? eref[idx] : T(0);
-      sE[1][j][lane] = ok ? eref[plane + idx] : T(0);
+      Ex[kk] = ok ? eref[idx] : T(0);
+      Ey[kk] = ok ? eref[plane + idx] : T(0);
+      sE[0][j][lane] = Ex[kk];
+      sE[1][j][lane] = Ey[kk];
+      sE[2][j][lane] = Ex[kk] + Ey[kk];
+      sE[3][j][lane] = Ey[kk] - Ex[kk];
     }
   }
 
@@ -385,6 +392,11 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   if (!perx && x == -1) xm = lane + 1;
   if (!perx && x == nx) xm = lane - 1;
   const bool ywall_lo = !pery && y0 - H < 0, ywall_hi = !pery && y0 + TY + H > ny;
+  // does the pull region (lanes and rows [2, 62) x [2, RR - 2)) hold a wall
+  // cell?  Tiles that hold none skip every boundary rule.
+  const int xa = tx * TXO - H + 2, xb = xa + kWave - 5, ya = y0 - H + 2, yb = ya + RR - 5;
+  const bool bnd = (!perx && ((xa <= 0 && xb >= 0) || (xa <= nx - 1 && xb >= nx - 1))) ||
+                   (!pery && ((ya <= 0 && yb >= 0) || (ya <= ny - 1 && yb >= ny - 1)));
 
   const T gam = k.gamma, omg = T(1) - k.gamma;
   const int lm = clampi(lane - 1, 0, kWave - 1), lp = clampi(lane + 1, 0, kWave - 1);
@@ -446,9 +458,6 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
       const int j = w + NW * kk;
       if (j < e + 2 || j >= RR - e - 2) continue;  // wave-uniform
       const int y = y0 - H + j;
-      const bool yreal = pery ? (y >= -H && y < ny + H) : (y >= 0 && y < ny);
-      const bool real = pl && xreal && yreal;
-      const int gy = ghost_map(clampi(y, -H, ny + H - 1), ny, pery);
       const int c = j - 1;
       const int lc = pl ? lane : 4;  // keep LDS indices in range on idle lanes
       T gi[8];
@@ -456,15 +465,33 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
       for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
       T ex = T(0), ey = T(0);
       if (SHIFT) {
-        ex = sE[0][j][lc];
-        ey = sE[1][j][lc];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          gi[q] += el_geq<T>(q, sE[0][j - cy8(q)][lc - cx8(q)] - ex, sE[1][j - cy8(q)][lc - cx8(q)] - ey);
+        // the source's reference minus this cell's, in the rest equilibrium
+        // of the population (el_geq), one LDS read per direction
+        ex = Ex[kk];
+        ey = Ey[kk];
+        const T sp = ex + ey, sm = ey - ex;
+        const T third = T(1.0 / 3.0), twelfth = T(1.0 / 12.0);
+        gi[0] += third * (sE[0][j][lc - 1] - ex);
+        gi[1] += third * (sE[1][j - 1][lc] - ey);
+        gi[2] -= third * (sE[0][j][lc + 1] - ex);
+        gi[3] -= third * (sE[1][j + 1][lc] - ey);
+        gi[4] += twelfth * (sE[2][j - 1][lc - 1] - sp);
+        gi[5] += twelfth * (sE[3][j - 1][lc + 1] - sm);
+        gi[6] -= twelfth * (sE[2][j + 1][lc + 1] - sp);
+        gi[7] -= twelfth * (sE[3][j + 1][lc - 1] - sm);
       }
-      const bool wl = real && !perx && x == 0, wr = real && !perx && x == nx - 1;
-      const bool wb = real && !pery && y == 0, wt = real && !pery && y == ny - 1;
-      if (wl || wr || wb || wt) {
+      bool wl = false, wr = false, wb = false, wt = false;
+      int gy = 0;
+      if (bnd) {
+        const bool yreal = pery ? (y >= -H && y < ny + H) : (y >= 0 && y < ny);
+        const bool real = pl && xreal && yreal;
+        gy = ghost_map(clampi(y, -H, ny + H - 1), ny, pery);
+        wl = real && !perx && x == 0;
+        wr = real && !perx && x == nx - 1;
+        wb = real && !pery && y == 0;
+        wt = real && !pery && y == ny - 1;
+      }
+      if (bnd && (wl || wr || wb || wt)) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int cx = cx8(q), cy = cy8(q);
