@@ -90,7 +90,9 @@ typedef struct {
   double r;                 /* explicit/implicit coupling ratio in [0, 1]; 0.5 = centred */
   int32_t levels;           /* multigrid levels L (0 = as many halvings as keep >= 2 cells) */
   int32_t K;                /* pre- and post-smoothing steps (>= 1) */
-  double gamma;             /* smoother under-relaxation in (0, 1) */
+  double gamma;             /* smoother under-relaxation in (0, 1] (eq. MG:smoother); 1 with
+                               levels = 1 is the plain pseudo-time stepping of Algorithm 1,
+                               2K applications per cycle */
   int32_t ne_fixed;         /* > 0: that many V-cycles per time step */
   double ne_tol;            /* ne_fixed == 0: stop when ||g - S(g)|| <= ne_tol ||g|| */
   int32_t ne_max;           /* ne_fixed == 0: at most this many V-cycles */

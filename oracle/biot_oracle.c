@@ -509,7 +509,7 @@ or_state *or_create(const or_problem *pb, int *err)
     *err = OR_ERR_ARG;
     if (pb->nx < 1 || pb->ny < 1 || pb->dx <= 0 || pb->dt <= 0 || pb->c0 <= 0 || pb->mu <= 0 ||
         pb->lambda + pb->mu <= 0 || pb->alpha < 0 || pb->alpha > 1 || pb->r < 0 || pb->r > 1 ||
-        pb->gamma <= 0 || pb->gamma >= 1 || pb->K < 1)
+        pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1)
         return NULL;
     for (int s = 0; s < 4; ++s) if (pb->el_type[s] < 0 || pb->el_type[s] > 3) return NULL;
     if ((pb->el_type[LEFT] == EL_PERIODIC) != (pb->el_type[RIGHT] == EL_PERIODIC)) return NULL;

@@ -84,7 +84,7 @@ bp_status validate(const bp_problem* p) {
   if (!(p->mu > 0) || !(p->lambda + p->mu > 0)) return fail(BP_ERR_ARG, "need mu > 0 and lambda + mu > 0");
   if (!(p->alpha >= 0 && p->alpha <= 1)) return fail(BP_ERR_ARG, "alpha must lie in [0, 1]");
   if (!(p->r >= 0 && p->r <= 1)) return fail(BP_ERR_ARG, "r must lie in [0, 1]");
-  if (!(p->gamma > 0 && p->gamma < 1)) return fail(BP_ERR_ARG, "gamma must lie in (0, 1)");
+  if (!(p->gamma > 0 && p->gamma <= 1)) return fail(BP_ERR_ARG, "gamma must lie in (0, 1]");
   if (p->K < 1) return fail(BP_ERR_ARG, "K must be >= 1");
   if (p->ne_fixed < 0) return fail(BP_ERR_ARG, "ne_fixed must be >= 0");
   if (p->ne_fixed == 0 && (!(p->ne_tol > 0) || p->ne_max < 1))

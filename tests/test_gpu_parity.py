@@ -150,6 +150,15 @@ def test_manufactured_time_dependent_loads(lbm):
     _say("manufactured worst rel", worst)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", STEP_TOL), ("fp32_shifted", 1e-5)])
+def test_plain_pseudo_time_stepping(lbm, prec, tol):
+    """Algorithm 1 (no multigrid): one level, gamma = 1, 16 plain elastic steps
+    per time step."""
+    p = P.loaded_strip(n=64, alpha=0.8, ne_fixed=8).replace(levels=1, gamma=1.0, K=1)
+    worst, _, _ = _compare_steps(lbm, p, 4, prec=prec, tol=tol)
+    _say("plain pseudo-time", prec, worst)
+
+
 def test_adaptive_cycles_follow_oracle(lbm):
     """Configuration 1 (Terzaghi 8x128, tolerance 1e-8, at most 50 cycles): the
     GPU's V-cycle counts are replayed by the oracle; the oracle's own adaptive
@@ -264,7 +273,7 @@ def test_full_size_loaded_strip_512(lbm):
 
 def test_invalid_problems_rejected(lbm):
     base = P.loaded_strip(n=16)
-    for bad in (dict(c0=0.0), dict(alpha=1.5), dict(gamma=1.0), dict(levels=6)):
+    for bad in (dict(c0=0.0), dict(alpha=1.5), dict(gamma=1.5), dict(levels=6)):
         with pytest.raises(lbm.BiotError):
             lbm.Solver(base.replace(**bad))
 

@@ -6,6 +6,7 @@ convergence order or stability pattern stated in the paper, an exact invariant
 (affine patch, mirror symmetry, zero load), or a brute-force linear solve.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -42,7 +43,7 @@ def single_cell(lam=0.3, mu=0.2, c0=1.0, alpha=0.0):
 
 # ------------------------------------------------------------------ tables
 def test_table3_inverts_moment_map_with_swapped_headers():
-    T = np.loadtxt("tests/golden/table3_backtransform.txt")
+    T = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table3_backtransform.txt"))
     M = moment_matrix()
     Tinv = np.linalg.inv(M)
     # printed column order 01, 10, ...: the first two headers are swapped
@@ -384,6 +385,43 @@ def test_multigrid_converges_to_brute_force_fixed_point(case):
     assert np.abs(g - gstar).max() < 1e-12 * max(1.0, np.abs(gstar).max())
 
 
+def test_plain_pseudo_time_stepping_reaches_the_same_fixed_point():
+    """Algorithm 1: plain pseudo-time steps (one level, gamma = 1) converge to
+    the fixed point of the elastic step that multigrid reaches."""
+    p = P.loaded_strip(n=8, alpha=0.9).replace(levels=1, gamma=1.0, K=1)
+    o = Oracle(p, threads=1)
+    rng = np.random.default_rng(11)
+    st = o.get_state()
+    o.set_state(f=rng.standard_normal(st["f"].shape) * 1e-2, g=st["g"], D1=rng.standard_normal(st["D1"].shape) * 1e-3,
+                D2=rng.standard_normal(st["D2"].shape) * 1e-3, step=3)
+    Ft = o.explicit_force()
+    gstar = _brute_fixed_point(o, 1, Ft)
+    g = np.zeros_like(gstar)
+    for _ in range(1200):
+        g = o.mg_cycle(1, g, None, Ft)
+    assert np.abs(g - gstar).max() < 1e-12 * np.abs(gstar).max()
+
+
+def test_plain_pseudo_time_needs_n_squared_steps():
+    """Without multigrid the pseudo-time iteration's contraction gap 1 - rho
+    shrinks like 1/N^2 (Sec. 3.4: the number of pseudo-time steps grows with
+    the grid; Sec. 3.5 removes that with multigrid)."""
+    gaps = []
+    for n in (8, 16, 32):
+        p = P.loaded_strip(n=n, alpha=0.0).replace(levels=1, gamma=1.0, K=1)
+        o = Oracle(p, threads=oracle_threads())
+        Ft = o.explicit_force()
+        g = np.random.default_rng(0).standard_normal((8, n, n))
+        res = []
+        for k in range(max(400, 3 * n * n) + 1):
+            if k % 10 == 0:
+                res.append(np.sqrt(np.sum((g - o.apply_elastic(1, g, None, Ft)) ** 2)))
+            g = o.mg_cycle(1, g, None, Ft)
+        gaps.append(1.0 - (res[-1] / res[-21]) ** (1.0 / 200))
+    ratios = [gaps[0] / gaps[1], gaps[1] / gaps[2]]
+    assert all(3.3 < q < 4.7 for q in ratios), (gaps, ratios)
+
+
 def test_vcycle_contraction_independent_of_grid():
     """Periodic elasticity: the V-cycle contraction factor stays bounded away
     from 1 as the grid is refined (Sec. 3.5: pseudo-time steps essentially
@@ -420,7 +458,7 @@ def test_adaptive_cycles_replay_bitwise():
 
 def test_invalid_problems_are_rejected():
     base = P.loaded_strip(n=8)
-    for bad in (dict(c0=0.0), dict(mu=-1.0), dict(alpha=1.5), dict(r=1.5), dict(gamma=1.0),
+    for bad in (dict(c0=0.0), dict(mu=-1.0), dict(alpha=1.5), dict(r=1.5), dict(gamma=1.5),
                 dict(levels=5), dict(kappa=-1.0)):
         with pytest.raises(OracleError):
             Oracle(base.replace(**bad))
