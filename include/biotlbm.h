@@ -98,6 +98,10 @@ typedef struct {
   int32_t ne_max;           /* ne_fixed == 0: at most this many V-cycles */
   bp_side side[4];
   int32_t prec;             /* bp_precision */
+  int32_t pressure_gradient; /* gradient of p in the explicit force: 0 = first moments of the
+                               flow populations (eq. pressure:gradient), 1 = central
+                               difference of p (eq. pressure:gradient:alternative); both
+                               add half the central gradient of the source */
 } bp_problem;
 
 typedef struct bp_solver bp_solver;

@@ -84,6 +84,7 @@ typedef struct {
     const int8_t *flow_type[4];   /* per boundary cell */
     const double *el_value[4];    /* 2 per boundary cell */
     const double *p_value[4];     /* 1 per boundary cell */
+    int32_t pressure_gradient;    /* 0: eq. pressure:gradient, 1: eq. pressure:gradient:alternative */
 } or_problem;
 
 typedef struct {
@@ -450,22 +451,45 @@ static void explicit_source(const or_state *o, double *st)
         st[c] = o->src[c] - (o->alpha / o->h) * ((1.0 - o->r) * (o->D1[c] - o->D2[c]) - o->r * o->D1[c]);
 }
 
-/* explicit force Ft = h^2 c0 f - alpha h grad p with the first-moment gradient of
- * eq. pressure:gradient evaluated with the explicit source part */
+/* explicit force Ft = h^2 c0 f - alpha h grad p, with the explicit source part.
+ * The gradient is either the first-moment form of eq. pressure:gradient,
+ *   grad p = -3 omega sum_i f_i c_i + (1/2) grad^c s,
+ * or the central difference of eq. pressure:gradient:alternative applied to
+ * p = sum_i f_i + s/2 (eq. pressure), i.e. grad^c(sum_i f_i) + (1/2) grad^c s;
+ * the s part, which carries the implicit coupling, is the same in both. */
 static void explicit_force(or_state *o, double *st, double *gst)
 {
     explicit_source(o, st);
     grad_central(o, o->nx, o->ny, st, gst);
+    double *gP = NULL;
+    if (o->pb.pressure_gradient == 1) {
+        double *P0 = (double *)malloc(sizeof(double) * o->n);
+        gP = (double *)malloc(sizeof(double) * 2 * o->n);
+        for (int c = 0; c < o->n; ++c) {
+            double s = 0.0;
+            for (int i = 0; i < 9; ++i) s += o->f[9 * c + i];
+            P0[c] = s;
+        }
+        grad_central(o, o->nx, o->ny, P0, gP);
+        free(P0);
+    }
     for (int c = 0; c < o->n; ++c) {
-        const double *fc = o->f + 9 * c;
-        double jx = 0.0, jy = 0.0;
-        for (int i = 0; i < 9; ++i) { jx += fc[i] * C9X[i]; jy += fc[i] * C9Y[i]; }
-        double om = o->om_f[c];
-        double gpx = -3.0 * om * jx + 0.5 * gst[2 * c];
-        double gpy = -3.0 * om * jy + 0.5 * gst[2 * c + 1];
+        double gpx, gpy;
+        if (gP) {
+            gpx = gP[2 * c] + 0.5 * gst[2 * c];
+            gpy = gP[2 * c + 1] + 0.5 * gst[2 * c + 1];
+        } else {
+            const double *fc = o->f + 9 * c;
+            double jx = 0.0, jy = 0.0;
+            for (int i = 0; i < 9; ++i) { jx += fc[i] * C9X[i]; jy += fc[i] * C9Y[i]; }
+            double om = o->om_f[c];
+            gpx = -3.0 * om * jx + 0.5 * gst[2 * c];
+            gpy = -3.0 * om * jy + 0.5 * gst[2 * c + 1];
+        }
         o->Ft[2 * c] = o->fbody[2 * c] - o->alpha * o->h * gpx;
         o->Ft[2 * c + 1] = o->fbody[2 * c + 1] - o->alpha * o->h * gpy;
     }
+    free(gP);
 }
 
 static double sumsq(const double *a, long n)
@@ -509,7 +533,7 @@ or_state *or_create(const or_problem *pb, int *err)
     *err = OR_ERR_ARG;
     if (pb->nx < 1 || pb->ny < 1 || pb->dx <= 0 || pb->dt <= 0 || pb->c0 <= 0 || pb->mu <= 0 ||
         pb->lambda + pb->mu <= 0 || pb->alpha < 0 || pb->alpha > 1 || pb->r < 0 || pb->r > 1 ||
-        pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1)
+        pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1 || pb->pressure_gradient < 0 || pb->pressure_gradient > 1)
         return NULL;
     for (int s = 0; s < 4; ++s) if (pb->el_type[s] < 0 || pb->el_type[s] > 3) return NULL;
     if ((pb->el_type[LEFT] == EL_PERIODIC) != (pb->el_type[RIGHT] == EL_PERIODIC)) return NULL;

@@ -41,7 +41,8 @@ class _Problem(C.Structure):
                 ("K", C.c_int32), ("gamma", C.c_double), ("ne_fixed", C.c_int32),
                 ("ne_tol", C.c_double), ("ne_max", C.c_int32),
                 ("el_type", C.c_int32 * 4), ("flow_type", C.POINTER(C.c_int8) * 4),
-                ("el_value", C.POINTER(C.c_double) * 4), ("p_value", C.POINTER(C.c_double) * 4)]
+                ("el_value", C.POINTER(C.c_double) * 4), ("p_value", C.POINTER(C.c_double) * 4),
+                ("pressure_gradient", C.c_int32)]
 
 
 _lib = None
@@ -109,6 +110,7 @@ class Oracle:
             pb.kappa_uniform = 0.0
         pb.r, pb.levels, pb.K, pb.gamma = p.r, p.levels, p.K, p.gamma
         pb.ne_fixed, pb.ne_tol, pb.ne_max = p.ne_fixed, p.ne_tol, p.ne_max
+        pb.pressure_gradient = int(getattr(p, "pressure_gradient", 0))
         for s in range(4):
             side = p.sides[s]
             fl = np.ascontiguousarray(side.flow, dtype=np.int8)

@@ -86,6 +86,8 @@ bp_status validate(const bp_problem* p) {
   if (!(p->r >= 0 && p->r <= 1)) return fail(BP_ERR_ARG, "r must lie in [0, 1]");
   if (!(p->gamma > 0 && p->gamma <= 1)) return fail(BP_ERR_ARG, "gamma must lie in (0, 1]");
   if (p->K < 1) return fail(BP_ERR_ARG, "K must be >= 1");
+  if (p->pressure_gradient != 0 && p->pressure_gradient != 1)
+    return fail(BP_ERR_ARG, "pressure_gradient must be 0 (first moments) or 1 (central difference)");
   if (p->ne_fixed < 0) return fail(BP_ERR_ARG, "ne_fixed must be >= 0");
   if (p->ne_fixed == 0 && (!(p->ne_tol > 0) || p->ne_max < 1))
     return fail(BP_ERR_ARG, "adaptive mode needs ne_tol > 0 and ne_max >= 1");
@@ -441,6 +443,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.h = p->dx;
   d.r = p->r;
   d.inv_c0h = 1.0 / (p->c0 * p->dx);
+  d.grad_central = p->pressure_gradient;
   for (int k = 0; k < 4; ++k) d.el[k] = p->side[k].el;
   d.f[0] = base + lo.off_f[0];
   d.f[1] = base + lo.off_f[1];

@@ -59,6 +59,7 @@ struct ProbD {
   double om_s, om_d, beta22, kD, cstar, gamma;
   double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
   int ntiles_fine;            // sweep tiles of the finest level
+  int grad_central;           // explicit force: central difference of p instead of first moments
   int ntiles_fine2;           // two-application sweep tiles of the finest level
   uint32_t* ttab;             // coarse tail: per-cell gather tables of levels 1.. (8 words per cell)
 };

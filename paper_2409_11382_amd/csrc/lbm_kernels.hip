@@ -851,16 +851,39 @@ __global__ __launch_bounds__(256) void k_force(CellL a) {
   double gx, gy;
   grad_c(st, gx, gy);
   const int64_t idx = (int64_t)c.y * V.pitch + c.x;
-  double jx = 0.0, jy = 0.0;
+  double px, py;  // gradient of p without its source part
+  if (P.grad_central) {
+    // central difference (eq. pressure:gradient:alternative) of the sum of the
+    // populations; shifted storage holds f - w p_ref, whose sum lacks p_ref
+    const T* pref = (const T*)P.pref;
+    double pv[3][3];
 #pragma unroll
-  for (int i = 1; i < 9; ++i) {
-    const double v = double(f[i * V.plane + idx]);
-    jx += v * cx9(i);
-    jy += v * cy9(i);
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
+        const int64_t k = (int64_t)ys * V.pitch + xs;
+        double sum = pref ? double(pref[k]) : 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
+        pv[dy + 1][dx + 1] = sum;
+      }
+    grad_c(pv, px, py);
+  } else {
+    // first moments of the populations (eq. pressure:gradient)
+    double jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const double v = double(f[i * V.plane + idx]);
+      jx += v * cx9(i);
+      jy += v * cy9(i);
+    }
+    const double om = P.omf ? P.omf[idx] : P.omf_u;
+    px = -3.0 * om * jx;
+    py = -3.0 * om * jy;
   }
-  const double om = P.omf ? P.omf[idx] : P.omf_u;
-  double Fx = -P.alpha * P.h * (-3.0 * om * jx + 0.5 * gx);
-  double Fy = -P.alpha * P.h * (-3.0 * om * jy + 0.5 * gy);
+  double Fx = -P.alpha * P.h * (px + 0.5 * gx);
+  double Fy = -P.alpha * P.h * (py + 0.5 * gy);
   if (P.fbody) {
     Fx += P.fbody[idx];
     Fy += P.fbody[V.plane + idx];

@@ -37,6 +37,12 @@ PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32,
               "fp32_shifted": PREC_FP32_SHIFTED, "fp64_shifted": PREC_FP64_SHIFTED}
 
 
+# pressure gradient of the explicit force: first moments of the flow
+# populations (eq. pressure:gradient) or the central difference of the pressure
+# (eq. pressure:gradient:alternative)
+GRAD_MOMENTS, GRAD_CENTRAL = 0, 1
+
+
 @dataclasses.dataclass
 class Side:
     """One side of the rectangular domain.
@@ -82,6 +88,7 @@ class Problem:
     ne_tol: float = 0.0                # used when ne_fixed == 0
     ne_max: int = 50
     name: str = ""
+    pressure_gradient: int = 0         # GRAD_MOMENTS or GRAD_CENTRAL
 
     # ---- helpers ---------------------------------------------------------
     @property

@@ -159,6 +159,22 @@ def test_plain_pseudo_time_stepping(lbm, prec, tol):
     _say("plain pseudo-time", prec, worst)
 
 
+def test_central_pressure_gradient_variant(lbm):
+    """Eq. pressure:gradient:alternative in the explicit force: the periodic
+    manufactured problem with time-dependent loads, and a walled problem (the
+    gradient's ghost values reflect at walls) in FP64 and FP32 shifted."""
+    M = P.Manufactured(32, alpha=1.0, r=0.5, K=2, ne_fixed=3)
+    pm = M.problem.replace(pressure_gradient=P.GRAD_CENTRAL)
+    worst, _, _ = _compare_steps(lbm, pm, 9, loads=M.loads, check_every=3)
+    _say("central gradient, periodic", worst)
+    pw = mixed_walls(124, 68, seed=4).replace(pressure_gradient=P.GRAD_CENTRAL, ne_fixed=3, K=4)
+    worst, _, _ = _compare_steps(lbm, pw, 6, check_every=3)
+    _say("central gradient, walls fp64", worst)
+    ps = P.loaded_strip(n=128, alpha=1.0, ne_fixed=3).replace(pressure_gradient=P.GRAD_CENTRAL)
+    worst, _, _ = _compare_steps(lbm, ps, 20, prec="fp32_shifted", tol=1e-5)
+    _say("central gradient, strip fp32 shifted", worst)
+
+
 def test_adaptive_cycles_follow_oracle(lbm):
     """Configuration 1 (Terzaghi 8x128, tolerance 1e-8, at most 50 cycles): the
     GPU's V-cycle counts are replayed by the oracle; the oracle's own adaptive
