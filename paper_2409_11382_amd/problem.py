@@ -188,6 +188,29 @@ def loaded_strip(n=512, E=1.0, nu=0.3, kappa=1.0, c0=1.0, alpha=1.0, load=1.0,
                    name=f"loaded_strip_{nx}x{ny}")
 
 
+# ---------------------------------------------------------------------------
+# Two-dimensional loading problem (Sec. 4.3), dimensional: domain (0, 100)^2,
+# final time 2e6, top drained with the traction (0, -1e4 (1 - cos(pi (x1 + 25)
+# / 50))), bottom clamped and impermeable, periodic in x1; E = 1e5, nu = 0.9
+# (plane stress), c0 = 1e-6, kappa = 1e-9, alpha = 1; N_T = N_x^2 time steps,
+# centred coupling with MG(3,4).
+# ---------------------------------------------------------------------------
+def loading_2d(n=128, steps=None, K=4, ne_fixed=3, r=0.5, levels=0) -> Problem:
+    length, t_final = 100.0, 2.0e6
+    h = length / n
+    nt = n * n if steps is None else steps
+    lam, mu = plane_stress_lame(1.0e5, 0.9)
+    x1 = (np.arange(n) + 0.5) * h
+    tval = np.zeros((n, 2))
+    tval[:, 1] = -1.0e4 * (1.0 - np.cos((x1 + 25.0) / 50.0 * math.pi))
+    top = Side(el=EL_TRACTION, flow=np.full(n, FLOW_DIRICHLET, dtype=np.int8), el_value=tval,
+               p_value=np.zeros(n))
+    bottom = Side.uniform(n, EL_DIRICHLET, FLOW_NOFLOW)
+    return Problem(nx=n, ny=n, dx=h, dt=t_final / nt, lam=lam, mu=mu, c0=1.0e-6, alpha=1.0, kappa=1.0e-9,
+                   sides=_sides_periodic_x(n, n, bottom, top), r=r, levels=levels, K=K, ne_fixed=ne_fixed,
+                   name=f"loading_2d_{n}")
+
+
 def lognormal_permeability(n: int, sigma_log=1.0, corr=32.0, seed=0, ny=None) -> np.ndarray:
     """ln kappa = sigma_log * Z with Z a zero-mean, unit-variance Gaussian random
     field of covariance exp(-r^2/corr^2) (corr in cells), made by FFT filtering of

@@ -8,7 +8,8 @@ multi-application launches and the coarse tail):
   shifted storage, a few steps against the oracle;
 - a sample of the 256-problem batch, each against the oracle and against a
   lone solve;
-- served requests drawn from the serving size range (128^2 .. 1024^2).
+- served requests drawn from the serving size range (128^2 .. 1024^2);
+- the two-dimensional loading problem of Sec. 4.3 at N_x = 128.
 """
 import sys
 
@@ -163,3 +164,25 @@ def test_served_requests_at_serving_sizes(lbm):
         d = (rel(got[k]["eta"], A["eta"]), rel(got[k]["p"], A["p"]))
         _say("served", k, p.nx, 3 + k, d)
         assert max(d) < ALONE_TOL, (k, d)
+
+
+def test_two_dimensional_loading_128(lbm):
+    """Sec. 4.3 at the paper's resolution (N_x = 128, dimensional inputs,
+    N_T = N_x^2): the first steps against the oracle."""
+    p = P.loading_2d(n=128)
+    nsteps = 10
+    o = Oracle(p, threads=oracle_threads())
+    o.step(nsteps)
+    B = o.fields()
+    s = lbm.Solver(p, "fp64")
+    s.step(nsteps)
+    e = _elementwise(s.fields(), B)
+    _say("2D loading fp64 element-wise", e)
+    assert e < STEP_TOL
+    s.close()
+    s = lbm.Solver(p, "fp32_shifted")
+    s.step(nsteps)
+    A = s.fields()
+    e32 = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]))
+    _say("2D loading fp32_shifted rel L2", e32)
+    assert max(e32) < FP32_TOL

@@ -292,6 +292,30 @@ def test_stability_pattern_of_the_couplings():
     assert not _grows(n, 1.0, 0.5)
 
 
+# ---------------------------------------------------- 2D loading (Sec. 4.3)
+def test_two_dimensional_loading_behaves_as_described():
+    """Sec. 4.3: the surface subsides under the larger load on the left and is
+    lifted on the right, the soil moves from the left half to the right one,
+    the early pressure below the surface is high on the left and low on the
+    right, and later the pressure decays while the whole surface subsides."""
+    p = P.loading_2d(n=32)
+    o = Oracle(p, threads=oracle_threads())
+    n = p.nx
+    x1 = (np.arange(n) + 0.5) * p.dx
+    i25, i50, i75 = (int(np.argmin(abs(x1 - v))) for v in (25.0, 50.0, 75.0))
+    o.step(int(round(2e4 / p.dt)))
+    F = o.fields()
+    s_left, s_right = F["eta"][1][-1][i25], F["eta"][1][-1][i75]
+    assert s_left < 0 < s_right
+    assert F["eta"][0][n // 2][i50] > 0
+    assert F["p"][-3][i25] > 3 * F["p"][-3][i75] > 0
+    pmax = np.abs(F["p"]).max()
+    o.step(int(round(2e5 / p.dt)) - int(round(2e4 / p.dt)))
+    G = o.fields()
+    assert np.abs(G["p"]).max() < pmax
+    assert G["eta"][1][-1][i25] < s_left and G["eta"][1][-1][i75] < s_right
+
+
 # -------------------------------------------------------------- Terzaghi
 def test_terzaghi_paper_parameters_give_unit_p0():
     """Sec. 4.2 states that its parameter choice implies p0 = 1."""
