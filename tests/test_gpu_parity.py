@@ -144,10 +144,22 @@ def test_fp64_steps_match_oracle(lbm, name):
     _say("  worst rel", worst)
 
 
-def test_manufactured_time_dependent_loads(lbm):
-    M = P.Manufactured(32, alpha=1.0, r=0.5, K=2, ne_fixed=3)
+@pytest.mark.parametrize("r,alpha", [(0.5, 1.0), (0.0, 0.5), (1.0, 0.7)])
+def test_manufactured_time_dependent_loads(lbm, r, alpha):
+    """Sec. 4.1's periodic problem with its time-dependent body force and
+    source, for the centred, explicit and implicit couplings (each at a
+    coupling strength the section reports stable)."""
+    M = P.Manufactured(32, alpha=alpha, r=r, K=2, ne_fixed=3)
     worst, _, _ = _compare_steps(lbm, M.problem, 12, loads=M.loads, check_every=3)
-    _say("manufactured worst rel", worst)
+    _say("manufactured r", r, "worst rel", worst)
+
+
+@pytest.mark.parametrize("alpha", [0.8, 1.0])
+def test_terzaghi_paper_parameters(lbm, alpha):
+    """Sec. 4.2's Terzaghi parameters (E = 1, nu = 0.8, p0 = 1) with MG(3,4)."""
+    p = P.terzaghi_paper(alpha, 64, nx=8, K=4)
+    worst, _, _ = _compare_steps(lbm, p, 10, check_every=5)
+    _say("terzaghi paper alpha", alpha, "worst rel", worst)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", STEP_TOL), ("fp32_shifted", 1e-5)])
