@@ -29,6 +29,7 @@ def simulate(rate: float, count: int, seed=2, ws_gib=32.0, max_slots=512, nmin=1
     pending = list(reqs)
     live = {}
     lat, finish = [], []
+    failures = []
     results = {}
     cell_steps = 0
     peak_active = 0
@@ -38,7 +39,7 @@ def simulate(rate: float, count: int, seed=2, ws_gib=32.0, max_slots=512, nmin=1
         while pending and pending[0][0] <= now:
             arr, prob, nsteps = pending.pop(0)
             t = srv.submit(prob, nsteps)
-            live[t] = (arr, prob.ncells, nsteps, len(results) + len(live))
+            live[t] = (arr, prob.ncells, nsteps, count - len(pending) - 1)
         if not live:
             time.sleep(max(0.0, pending[0][0] - now))
             continue
@@ -48,7 +49,11 @@ def simulate(rate: float, count: int, seed=2, ws_gib=32.0, max_slots=512, nmin=1
             st, _ = srv.poll(t)
             if st in (lbm.REQ_DONE, lbm.REQ_FAILED):
                 arr, cells, nsteps, idx = live.pop(t)
-                out = srv.result(t)
+                try:
+                    out = srv.result(t)
+                except lbm.BiotError as e:  # a failed request is reported, the others go on
+                    failures.append({"request": idx, "error": str(e)})
+                    out = None
                 done = time.perf_counter() - t0
                 lat.append(done - arr)
                 finish.append(done)
@@ -67,6 +72,7 @@ def simulate(rate: float, count: int, seed=2, ws_gib=32.0, max_slots=512, nmin=1
         "mlups": round(cell_steps / makespan / 1e6, 2),
         "peak_active": peak_active,
         "makespan_s": round(makespan, 3),
+        "failed": failures,
     }
     return (summary, results) if keep_results else summary
 

@@ -186,3 +186,19 @@ def test_two_dimensional_loading_128(lbm):
     e32 = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]))
     _say("2D loading fp32_shifted rel L2", e32)
     assert max(e32) < FP32_TOL
+
+
+def test_heterogeneous_2048_full_run_fp32_against_fp64(lbm):
+    """Configuration 3's full 1000 steps: FP32 shifted storage against the GPU
+    FP64 path (which matches the oracle element-wise in
+    test_heterogeneous_2048); the oracle itself would take hours here."""
+    p = P.heterogeneous_strip(n=2048, ne_fixed=3, K=4)
+    F = {}
+    for prec in ("fp64", "fp32_shifted"):
+        s = lbm.Solver(p, prec)
+        s.step(1000)
+        F[prec] = s.fields()
+        s.close()
+    e = (rel(F["fp32_shifted"]["eta"], F["fp64"]["eta"]), rel(F["fp32_shifted"]["p"], F["fp64"]["p"]))
+    _say("2048 after 1000 steps, fp32 shifted vs fp64", e)
+    assert max(e) < FP32_TOL

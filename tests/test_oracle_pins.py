@@ -316,6 +316,30 @@ def test_two_dimensional_loading_behaves_as_described():
     assert G["eta"][1][-1][i25] < s_left and G["eta"][1][-1][i75] < s_right
 
 
+def _strip_grows(kappa, grad, dt_h2, n=32, steps=1200):
+    p = P.loaded_strip(n=n, alpha=1.0, kappa=kappa, dt=dt_h2 / (n * n)).replace(pressure_gradient=grad)
+    o = Oracle(p, threads=oracle_threads())
+    o.step(steps // 2)
+    a = np.abs(o.fields()["p"]).max()
+    o.step(steps // 2)
+    b = np.abs(o.fields()["p"]).max()
+    return (not np.isfinite(b)) or b > 10 * max(a, 1.0)
+
+
+def test_first_moment_gradient_unstable_as_omega_f_nears_two():
+    """A finding outside the paper's tested range, behind two workload choices:
+    with the centred coupling at alpha = 1, the first-moment pressure gradient
+    (eq. pressure:gradient) goes unstable when small kappa drives omega_f
+    towards 2 (kappa = 0.02, dt = h^2/4: omega_f = 1.94); the central
+    difference (eq. pressure:gradient:alternative) stays stable there, and so
+    does the first-moment gradient at the time step that sets the lattice
+    diffusion number to 1/4 (omega_f = 0.8)."""
+    assert _strip_grows(0.02, P.GRAD_MOMENTS, 0.25)
+    assert not _strip_grows(0.02, P.GRAD_CENTRAL, 0.25)
+    assert not _strip_grows(0.02, P.GRAD_MOMENTS, 0.25 / 0.02)
+    assert not _strip_grows(1.0, P.GRAD_MOMENTS, 0.25)
+
+
 # -------------------------------------------------------------- Terzaghi
 def test_terzaghi_paper_parameters_give_unit_p0():
     """Sec. 4.2 states that its parameter choice implies p0 = 1."""
