@@ -49,8 +49,9 @@ typedef enum {
 } bp_status;
 
 /* population storage and collision precision; "shifted" stores populations as
- * offsets from a per-cell displacement / pressure reference (re-based every
- * step).  Divergence fields, the coupling source, residual norms and the
+ * offsets from a per-cell displacement / pressure reference (re-based at the
+ * start of every step, the displacement again before every later V-cycle of
+ * the step).  Divergence fields, the coupling source, residual norms and the
  * coarsest multigrid level are FP64 in every mode. */
 typedef enum { BP_FP64 = 0, BP_FP32 = 1, BP_FP32_SHIFTED = 2, BP_FP64_SHIFTED = 3 } bp_precision;
 

@@ -509,7 +509,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
 }
 
 // ---------------------------------------------------------------- engine
-enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
 
 struct Op {
   OpKind kind;
@@ -815,12 +815,19 @@ Op flow_op(Engine& E) {
   return o;
 }
 
-void build_step_ops(Engine& E) {
-  std::vector<Op>& ops = E.step_ops;
+// one time step.  Shifted storage re-bases at the start of the step and the
+// displacement again before every later V-cycle: the offsets then carry only
+// what one cycle changes.  Offsets that carry a whole step's change (early
+// steps move the solution by tens of per cent) lose in FP32 the stress moments,
+// differences of neighbouring offsets, in proportion to the grid size.
+void build_step_ops(Engine& E, std::vector<Op>& ops) {
   ops.clear();
   if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
   ops.push_back(cell_op(E, OP_FORCE));
-  for (int j = 0; j < E.ne; ++j) add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse);
+  for (int j = 0; j < E.ne; ++j) {
+    if (E.shift && j > 0) ops.push_back(cell_op(E, OP_REBASE_EL));
+    add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse);
+  }
   if (E.ne > 0) {
     Op f = prob_op(E, OP_FINALIZE);
     f.pl.fused = (E.fuse && E.K >= 2) ? 1 : 0;  // the last post-smoothing launch was a pair
@@ -874,7 +881,11 @@ hipError_t run_op(const Engine& E, const Op& o) {
       if (o.cdbl) return sweep_launch<float, double>(o, s);
       return sweep_launch<float, float>(o, s);
     case OP_FORCE: return E.fdbl ? launch_force<double>(o.cl, o.count, s) : launch_force<float>(o.cl, o.count, s);
-    case OP_REBASE: return E.fdbl ? launch_rebase<double>(o.cl, o.count, s) : launch_rebase<float>(o.cl, o.count, s);
+    case OP_REBASE:
+    case OP_REBASE_EL: {
+      const bool flow = o.kind == OP_REBASE;
+      return E.fdbl ? launch_rebase<double>(o.cl, o.count, flow, s) : launch_rebase<float>(o.cl, o.count, flow, s);
+    }
     case OP_INIT: return E.fdbl ? launch_init<double>(o.cl, o.count, s) : launch_init<float>(o.cl, o.count, s);
     case OP_FLOW:
       if (E.fdbl) return E.shift ? launch_tflow<double, true>(o.cl, o.count, s) : launch_tflow<double, false>(o.cl, o.count, s);
@@ -903,7 +914,7 @@ bp_status build_graph(Engine& E) {
     E.graph = nullptr;
   }
   E.graph_valid = false;
-  build_step_ops(E);
+  build_step_ops(E, E.step_ops);
   if (!E.use_graph || !E.stream) {
     E.graph_valid = true;
     return BP_OK;
@@ -988,6 +999,7 @@ bp_status adaptive_step(Engine& E) {
   for (;;) {
     ops.clear();
     if (j >= 1) {
+      if (E.shift) ops.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
       add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 1);
       ops.push_back(prob_op(E, OP_FINALIZE));
       BPCHK(run_ops(E, ops));

@@ -135,7 +135,7 @@ hipError_t launch_force(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
 hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
-hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s);
+hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
 

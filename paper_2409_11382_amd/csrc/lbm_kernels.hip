@@ -939,8 +939,9 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 }
 
 // re-basing of the shifted storage: move the per-cell references to the
-// current displacement and pressure so the stored offsets stay small
-template <typename T>
+// current displacement (and, with FLOW, pressure) so the stored offsets stay
+// small
+template <typename T, bool FLOW>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
@@ -959,6 +960,7 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   T* eref = (T*)P.eref;
   eref[idx] += m10;
   eref[V.plane + idx] += m01;
+  if (!FLOW) return;
   T* f = (T*)P.f[(*P.phase) & 1];
   T fv[9];
   T p = T(0);
@@ -1030,9 +1032,12 @@ hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s) {
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s) {
+hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rebase<T>), dim3(ntiles), dim3(256), 0, s, a);
+  if (flow)
+    hipLaunchKernelGGL((k_rebase<T, true>), dim3(ntiles), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_rebase<T, false>), dim3(ntiles), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, bool SHIFT>
@@ -1546,8 +1551,8 @@ template hipError_t launch_force<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_force<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_init<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_init<double>(const CellL&, int, hipStream_t);
-template hipError_t launch_rebase<float>(const CellL&, int, hipStream_t);
-template hipError_t launch_rebase<double>(const CellL&, int, hipStream_t);
+template hipError_t launch_rebase<float>(const CellL&, int, bool, hipStream_t);
+template hipError_t launch_rebase<double>(const CellL&, int, bool, hipStream_t);
 template hipError_t launch_extract<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<float, true>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<double, false>(const CellL&, int, hipStream_t);
