@@ -183,8 +183,9 @@ bp_status bp_destroy(bp_solver *s);
  * must share the precision, K and the fixed number of V-cycles; grids,
  * parameters and boundary data may differ.  Each problem's arithmetic is that
  * of solving it alone; results are bitwise identical when the batch leaves the
- * launch variants unchanged (a depth takes four-application launches or fuses
- * the restriction according to the cells it covers in all), and otherwise
+ * launch variants unchanged (a depth takes four-application launches, fuses
+ * the restriction and picks the region width of four applications with the
+ * restriction according to the cells it covers in all), and otherwise
  * agree to rounding (operations are fused differently in the variants). */
 typedef struct bp_batch bp_batch;
 bp_status bp_batch_workspace_bytes(const bp_problem *probs, int32_t n, size_t *device_bytes);

@@ -226,6 +226,7 @@ size_t tile_entries_for(const Layout& lo) {
   {
     t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
     for (int A = 2; A <= 5; ++A) t += (size_t)sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, A);
+    t += (size_t)sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 5, true);  // either width of A = 5
   }
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
@@ -522,6 +523,7 @@ struct Op {
   ProbL pl{};
   TailL tl{};
   int count = 0;          // tiles / problems
+  bool wide = false;      // four applications with restriction on 64-column regions
 };
 
 // tile-list key of a depth: full set or restriction set, one of three
@@ -545,15 +547,21 @@ int set_apps(int set) {
 // latency-bound: there the restriction joins the last pre-smoothing launch
 constexpr int64_t kFuseResCells = 512 * 512;
 // a depth whose launches cover at most this many cells in all takes four
-// applications per launch: its tiles (48 x 16 outputs, one 1024-thread block
-// per CU) fit one round over the 256 CUs, the launch is latency-bound and the
-// wider halo costs little there
+// applications per launch: the launch is bound by the dependent work of one
+// block, and its 32 x 32 regions (16 x 16 outputs) put 256 blocks on the 256
+// CUs at 256^2 cells; the redundant halo work costs little there
+// (BIOT_QUAD_MAX_CELLS overrides the bound)
 constexpr int64_t kQuadMaxCells = 256 * 256;
+// above this many cells in all, a depth's launch of four applications with
+// the restriction takes the 64-column regions: 12 x 12 outputs of the narrow
+// region would need about two blocks per CU there
+constexpr int64_t kQuadNarrowResCells = 128 * 128;
 struct DepthLists {
   int off[8][3] = {};
   int cnt[8][3] = {};
   bool quad = false;  // four applications per launch
   bool fres = false;  // restriction fused into the last pre-smoothing launch
+  bool qwide = false; // its four-application form on 64-column regions
   int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
@@ -579,6 +587,7 @@ struct Engine {
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
+  int64_t quad_max_cells = kQuadMaxCells;
   bool fuse_res = true;  // restriction fused into pre-smoothing on latency-bound depths
   double* host_pin = nullptr;
 };
@@ -623,6 +632,19 @@ bp_status engine_upload(Engine& E) {
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
+    int64_t depth_cells = 0;
+    for (size_t i = 0; i < np; ++i) {
+      const Prob& P = *E.probs[i];
+      const int l = P.L - d, td = P.lo.tail_depth;
+      if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
+    }
+    E.depth[d].quad = E.quad && depth_cells <= E.quad_max_cells;
+    E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
+    E.depth[d].qwide = depth_cells > kQuadNarrowResCells;
+    for (size_t i = 0; i < np; ++i) {  // tiles along x of the level at this depth, by its A = 5 width
+      const int l = E.probs[i]->L - d;
+      if (l >= 1) pd[i].lv[l].tiles_xn[5] = sweepn_tiles_x(E.probs[i]->lo.lv[l].nx, 5, E.depth[d].qwide);
+    }
     for (int set = 0; set < 8; ++set)
       for (int g = 0; g < 3; ++g) {
         E.depth[d].off[set][g] = (int)tiles.size();
@@ -633,20 +655,14 @@ bp_status engine_upload(Engine& E) {
           if (l < 1 || (set < 4 && (set & 1) && l < 2) || tgroup(E, P, d) != g) continue;
           if ((set < 2 || set >= kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
           const LevelLay& v = P.lo.lv[l];
-          const int nt = set >= kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, set_apps(set)) : sweep_tiles(v.nx, v.ny);
+          const int A = set_apps(set);
+          const int nt = set >= kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, A, A == 5 && E.depth[d].qwide)
+                                          : sweep_tiles(v.nx, v.ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
         if (E.xcd_order) xcd_order(tiles, E.depth[d].off[set][g]);
         E.depth[d].cnt[set][g] = (int)tiles.size() - E.depth[d].off[set][g];
       }
-    int64_t depth_cells = 0;
-    for (size_t i = 0; i < np; ++i) {
-      const Prob& P = *E.probs[i];
-      const int l = P.L - d, td = P.lo.tail_depth;
-      if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
-    }
-    E.depth[d].quad = E.quad && depth_cells <= kQuadMaxCells;
-    E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
     E.depth[d].tail_off = (int)tiles.size();
     for (size_t i = 0; i < np; ++i)
       if (E.probs[i]->lo.tail_depth == d && d > 0) tiles.push_back(make_int2((int)i, 0));
@@ -703,6 +719,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     Op o;
     o.kind = OP_SWEEP;
     o.apps = set_apps(set);
+    o.wide = o.apps == 5 && E.depth[d].qwide;
     o.mode = mode;
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
@@ -842,6 +859,11 @@ hipError_t sweep_launch(const Op& o, hipStream_t s) {
   const bool fine = o.sw.depth == 0;
   switch (o.apps) {
     case 5:
+      if (o.wide) {
+        if (!fine) return launch_tsweep2<T, Tc, false, false, 4, true, true>(o.sw, o.count, s);
+        return o.shift ? launch_tsweep2<T, Tc, true, true, 4, true, true>(o.sw, o.count, s)
+                       : launch_tsweep2<T, Tc, true, false, 4, true, true>(o.sw, o.count, s);
+      }
       if (!fine) return launch_tsweep2<T, Tc, false, false, 4, true>(o.sw, o.count, s);
       return o.shift ? launch_tsweep2<T, Tc, true, true, 4, true>(o.sw, o.count, s)
                      : launch_tsweep2<T, Tc, true, false, 4, true>(o.sw, o.count, s);
@@ -953,6 +975,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_QUAD")) E.quad = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_QUAD_MAX_CELLS")) E.quad_max_cells = std::atoll(e);
   if (const char* e = std::getenv("BIOT_NO_FUSE_RES")) E.fuse_res = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");

@@ -106,27 +106,39 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
 // Multi-application sweeps, by applications per launch A: 2 (a pair of
 // smoothing applications), 3 (a pair, then the residual of its result
 // restricted to the coarser level), 4 (four smoothing applications) and 5
-// (four, then the restricted residual).  A tile has (64 - 4 A) x
-// (WAVES NK - 4 A) outputs with NK rows per wave.  Few rows per wave keep each
-// wave's chain of dependent work short, which is what bounds the smaller grids.
+// (four, then the restricted residual).  A region is COLS x (WAVES NK 64/COLS)
+// cells with NK row indices per wave, each covering 64/COLS rows of COLS
+// cells; a tile has (COLS - 4 A) x (rows - 4 A) outputs.  Pairs take 64-cell
+// rows.  Four applications are used only on depths of few cells, where the
+// launch is bound by the dependent work of one block rather than by HBM: a
+// 32 x 32 region (16 x 16 outputs) spreads such a depth over about four times
+// as many compute units as a 64-column one, at twice its redundant halo work.
+// With the restriction (A = 5, halo 10) a 32 x 32 region keeps only 12 x 12
+// outputs; the WIDE form (64 x 32 region, 44 x 12 outputs) serves the larger
+// of the depths that take four applications.
 template <int A>
 __host__ __device__ constexpr int sweepn_waves() { return A <= 3 ? 8 : 16; }
 template <typename T, int A>
 __host__ __device__ constexpr int sweepn_rows() {
-  return A == 2 ? (sizeof(T) == 8 ? 2 : 3) : (A == 3 ? 3 : 2);
+  return A == 2 ? (sizeof(T) == 8 ? 2 : 3) : (A == 3 ? 3 : 1);
 }
-inline int sweepn_tile_x(int A) { return kWave - 4 * A; }
+template <int A>
+__host__ __device__ constexpr int sweepn_cols() { return A <= 3 ? kWave : 32; }
+inline int sweepn_tile_x(int A, bool wide = false) {
+  return ((A <= 3 || wide) ? sweepn_cols<2>() : sweepn_cols<4>()) - 4 * A;
+}
 inline int sweepn_tile_y(int A, bool dbl) {
   int rr = 0;
   switch (A) {
     case 2: rr = sweepn_waves<2>() * (dbl ? sweepn_rows<double, 2>() : sweepn_rows<float, 2>()); break;
     case 3: rr = sweepn_waves<3>() * sweepn_rows<float, 3>(); break;
-    case 4: rr = sweepn_waves<4>() * sweepn_rows<float, 4>(); break;
-    default: rr = sweepn_waves<5>() * sweepn_rows<float, 5>(); break;
+    case 4: rr = sweepn_waves<4>() * sweepn_rows<float, 4>() * (kWave / sweepn_cols<4>()); break;
+    default: rr = sweepn_waves<5>() * sweepn_rows<float, 5>() * (kWave / sweepn_cols<5>()); break;
   }
   return rr - 4 * A;
 }
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
+// WIDE (APPS = 4 with RES only): 64-column regions of 16 waves x 2 rows
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE = false>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
@@ -151,10 +163,13 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 
 inline int sweep_tiles_x(int nx) { return (nx + kTileX - 1) / kTileX; }
 inline int sweep_tiles(int nx, int ny) { return sweep_tiles_x(nx) * ((ny + kTileY - 1) / kTileY); }
-inline int sweepn_tiles_x(int nx, int apps) { return (nx + sweepn_tile_x(apps) - 1) / sweepn_tile_x(apps); }
-inline int sweepn_tiles(int nx, int ny, bool dbl, int apps) {
+inline int sweepn_tiles_x(int nx, int apps, bool wide = false) {
+  return (nx + sweepn_tile_x(apps, wide) - 1) / sweepn_tile_x(apps, wide);
+}
+// the row count of a WIDE region equals the narrow one's: 16 x 2 = 16 x 1 x 2
+inline int sweepn_tiles(int nx, int ny, bool dbl, int apps, bool wide = false) {
   const int ty = sweepn_tile_y(apps, dbl);
-  return sweepn_tiles_x(nx, apps) * ((ny + ty - 1) / ty);
+  return sweepn_tiles_x(nx, apps, wide) * ((ny + ty - 1) / ty);
 }
 inline int cell_blocks(int nx, int ny) { return ((nx + kCellBX - 1) / kCellBX) * ((ny + kCellBY - 1) / kCellBY); }
 

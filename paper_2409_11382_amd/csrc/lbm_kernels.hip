@@ -298,20 +298,23 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 // the first ghost row/column of D must be restored by reflection (the loaded
 // ghosts were reflected copies; after an application they hold unused
 // values): columns by a lane permutation, rows through LDS.
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE>
 __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(SweepL a) {
   constexpr int A = APPS + (RES ? 1 : 0);
+  static_assert(!WIDE || A == 5, "the wide region serves four applications with the restriction");
   constexpr int NW = sweepn_waves<A>();
-  constexpr int NK = sweepn_rows<T, A>();
-  constexpr int H = 2 * A;       // halo
-  constexpr int RR = NW * NK;    // region rows
-  constexpr int TY = RR - 2 * H; // output rows
-  constexpr int TXO = kWave - 2 * H;
-  __shared__ T sD[RR][kWave];
-  __shared__ T sS[8][RR - 2][kWave];
+  constexpr int NK = WIDE ? 2 : sweepn_rows<T, A>();
+  constexpr int H = 2 * A;         // halo
+  constexpr int RX = WIDE ? kWave : sweepn_cols<A>();  // region columns
+  constexpr int S = kWave / RX;    // rows per wave and row index kk
+  constexpr int RR = NW * NK * S;  // region rows
+  constexpr int TY = RR - 2 * H;   // output rows
+  constexpr int TXO = RX - 2 * H;
+  __shared__ T sD[RR][RX];
+  __shared__ T sS[8][RR - 2][RX];
   // shifted storage: reference ex, ey and the sums ex + ey, ey - ex that the
   // diagonal pulls' corrections need
-  __shared__ T sE[SHIFT ? 4 : 1][SHIFT ? RR : 1][kWave];
+  __shared__ T sE[SHIFT ? 4 : 1][SHIFT ? RR : 1][RX];
   __shared__ double sRed[2 * NW];
 
   const int2 te = a.tiles[blockIdx.x];
@@ -323,7 +326,8 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   const int tiles_x = V.tiles_xn[A];
   const int tx = te.y % tiles_x, ty = te.y / tiles_x;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const int x = tx * TXO - H + lane;
+  const int col = lane & (RX - 1), sub = lane / RX;  // a wave holds S rows of RX cells
+  const int x = tx * TXO - H + col;
   const int y0 = ty * TY;
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
   // a single reflection covers ghosts up to nx cells out; farther ones (levels
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   // ---- load the region (ghosts as reflected or periodic copies)
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {
-    const int j = w + NW * kk;
+    const int j = (w + NW * kk) * S + sub;
     const int y = y0 - H + j;
     const bool ok = col_ok && y >= -H && y < ny + H && (pery || (y >= -ny && y < 2 * ny));
     const int gy = ok ? ghost_map(y, ny, pery) : 0;
@@ -380,10 +384,10 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
     if (SHIFT) {
       Ex[kk] = ok ? eref[idx] : T(0);
       Ey[kk] = ok ? eref[plane + idx] : T(0);
-      sE[0][j][lane] = Ex[kk];
-      sE[1][j][lane] = Ey[kk];
-      sE[2][j][lane] = Ex[kk] + Ey[kk];
-      sE[3][j][lane] = Ey[kk] - Ex[kk];
+      sE[0][j][col] = Ex[kk];
+      sE[1][j][col] = Ey[kk];
+      sE[2][j][col] = Ex[kk] + Ey[kk];
+      sE[3][j][col] = Ey[kk] - Ex[kk];
     }
   }
 
@@ -392,46 +396,46 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   if (!perx && x == -1) xm = lane + 1;
   if (!perx && x == nx) xm = lane - 1;
   const bool ywall_lo = !pery && y0 - H < 0, ywall_hi = !pery && y0 + TY + H > ny;
-  // does the pull region (lanes and rows [2, 62) x [2, RR - 2)) hold a wall
-  // cell?  Tiles that hold none skip every boundary rule.
-  const int xa = tx * TXO - H + 2, xb = xa + kWave - 5, ya = y0 - H + 2, yb = ya + RR - 5;
+  // does the pull region (columns and rows [2, RX - 2) x [2, RR - 2)) hold a
+  // wall cell?  Tiles that hold none skip every boundary rule.
+  const int xa = tx * TXO - H + 2, xb = xa + RX - 5, ya = y0 - H + 2, yb = ya + RR - 5;
   const bool bnd = (!perx && ((xa <= 0 && xb >= 0) || (xa <= nx - 1 && xb >= nx - 1))) ||
                    (!pery && ((ya <= 0 && yb >= 0) || (ya <= ny - 1 && yb >= ny - 1)));
 
   const T gam = k.gamma, omg = T(1) - k.gamma;
-  const int lm = clampi(lane - 1, 0, kWave - 1), lp = clampi(lane + 1, 0, kWave - 1);
+  const int lm = clampi(col - 1, 0, RX - 1), lp = clampi(col + 1, 0, RX - 1);
   double acc_r = 0.0, acc_g = 0.0;
 
 #pragma unroll
   for (int app = 0; app < A; ++app) {
-    const int e = 2 * app;  // rows / lanes [e, RR - e) hold a valid iterate
+    const int e = 2 * app;  // rows / columns [e, RR - e) hold a valid iterate
     // ---- D(g)
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + NW * kk;
+      const int j = (w + NW * kk) * S + sub;
       T dv = k.kD * el_ms(G[kk]);
       if (app > 0) dv = __shfl(dv, xm, kWave);
-      if (j >= e && j < RR - e) sD[j][lane] = dv;
+      if (j >= e && j < RR - e) sD[j][col] = dv;
     }
     if (app > 0 && (ywall_lo || ywall_hi)) {
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < NK; ++kk) {
-        const int j = w + NW * kk;
+        const int j = (w + NW * kk) * S + sub;
         const int y = y0 - H + j;
-        if (ywall_lo && y == -1) sD[j][lane] = sD[j + 1][lane];
-        if (ywall_hi && y == ny) sD[j][lane] = sD[j - 1][lane];
+        if (ywall_lo && y == -1) sD[j][col] = sD[j + 1][col];
+        if (ywall_hi && y == ny) sD[j][col] = sD[j - 1][col];
       }
     }
     __syncthreads();
     // ---- self-force and collision
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + NW * kk;
+      const int j = (w + NW * kk) * S + sub;
       if (j >= e + 1 && j < RR - e - 1) {
-        T v[3][3] = {{sD[j - 1][lm], sD[j - 1][lane], sD[j - 1][lp]},
-                     {sD[j][lm], sD[j][lane], sD[j][lp]},
-                     {sD[j + 1][lm], sD[j + 1][lane], sD[j + 1][lp]}};
+        T v[3][3] = {{sD[j - 1][lm], sD[j - 1][col], sD[j - 1][lp]},
+                     {sD[j][lm], sD[j][col], sD[j][lp]},
+                     {sD[j + 1][lm], sD[j + 1][col], sD[j + 1][lp]}};
         T gx_, gy_;
         grad_c(v, gx_, gy_);
         T u[8], s8[8];
@@ -447,19 +451,19 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
         }
         el_collide(u, fx, fy, k, s8);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sS[q][j - 1][lane] = s8[q];
+        for (int q = 0; q < 8; ++q) sS[q][j - 1][col] = s8[q];
       }
     }
     __syncthreads();
     // ---- pull-stream with the boundary rules, under-relaxation
-    const bool pl = lane >= e + 2 && lane < kWave - e - 2;
+    const bool pl = col >= e + 2 && col < RX - e - 2;
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + NW * kk;
-      if (j < e + 2 || j >= RR - e - 2) continue;  // wave-uniform
+      const int j = (w + NW * kk) * S + sub;
+      if (j < e + 2 || j >= RR - e - 2) continue;  // uniform over each row of a wave
       const int y = y0 - H + j;
       const int c = j - 1;
-      const int lc = pl ? lane : 4;  // keep LDS indices in range on idle lanes
+      const int lc = pl ? col : 4;  // keep LDS indices in range on idle lanes
       T gi[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
@@ -544,10 +548,11 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
           gi[q] = v;
         }
       }
-      const bool out = pl && x >= 0 && x < nx && y >= 0 && y < ny && lane >= H && lane < kWave - H &&
+      const bool out = pl && x >= 0 && x < nx && y >= 0 && y < ny && col >= H && col < RX - H &&
                        j >= H && j < RR - H;
       if (RES && app == A - 1) {
-        // residual of the smoothed iterate, summed over lane pairs (x, x + 1);
+        // residual of the smoothed iterate, summed over lane pairs (x, x + 1)
+        // (both lanes of a pair lie in one row);
         // the row pairs are summed through LDS below
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -589,22 +594,22 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
     __syncthreads();  // every pull has read sS
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + NW * kk;
+      const int j = (w + NW * kk) * S + sub;
       if (j >= H && j < RR - H) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sS[q][j][lane] = G[kk][q];
+        for (int q = 0; q < 8; ++q) sS[q][j][col] = G[kk][q];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
-      const int j = w + NW * kk;
+      const int j = (w + NW * kk) * S + sub;
       const int y = y0 - H + j;
-      if (rc && j >= H && j < RR - H && (y & 1) == 0 && y < ny && lane >= H && lane < kWave - H && x >= 0 &&
+      if (rc && j >= H && j < RR - H && (y & 1) == 0 && y < ny && col >= H && col < RX - H && x >= 0 &&
           x < nx && (x & 1) == 0) {
         const int64_t cidx = (int64_t)(y >> 1) * cpitch + (x >> 1);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) rc[q * cplane + cidx] = Tc(sS[q][j][lane] + sS[q][j + 1][lane]);
+        for (int q = 0; q < 8; ++q) rc[q * cplane + cidx] = Tc(sS[q][j][col] + sS[q][j + 1][col]);
       }
     }
   }
@@ -629,10 +634,10 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   }
 }
 
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES>), dim3(ntiles),
+  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, WIDE>), dim3(ntiles),
                      dim3(kWave * sweepn_waves<APPS + (RES ? 1 : 0)>()), 0, s, a);
   return hipGetLastError();
 }
@@ -1524,7 +1529,9 @@ BIOT_SWEEP(double, double)
   template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, hipStream_t);  \
   template hipError_t launch_tsweep2<T, Tc, false, false, 4, true>(const SweepL&, int, hipStream_t);   \
   template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true>(const SweepL&, int, hipStream_t);
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true, true>(const SweepL&, int, hipStream_t); \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true, true>(const SweepL&, int, hipStream_t);
 BIOT_SWEEPN(float, float)
 BIOT_SWEEPN(float, double)
 BIOT_SWEEPN(double, double)
@@ -1533,6 +1540,8 @@ template hipError_t launch_tsweep2<float, float, true, true, 4, false>(const Swe
 template hipError_t launch_tsweep2<float, float, true, true, 4, true>(const SweepL&, int, hipStream_t);
 template hipError_t launch_tsweep2<float, double, true, true, 4, false>(const SweepL&, int, hipStream_t);
 template hipError_t launch_tsweep2<float, double, true, true, 4, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 4, true, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, true, true>(const SweepL&, int, hipStream_t);
 // FP64 shifted storage has no LDS room for four applications; the schedule
 // never asks for them (these stubs keep the dispatch table complete)
 template <>
@@ -1541,6 +1550,10 @@ hipError_t launch_tsweep2<double, double, true, true, 4, false>(const SweepL&, i
 }
 template <>
 hipError_t launch_tsweep2<double, double, true, true, 4, true>(const SweepL&, int, hipStream_t) {
+  return hipErrorInvalidConfiguration;
+}
+template <>
+hipError_t launch_tsweep2<double, double, true, true, 4, true, true>(const SweepL&, int, hipStream_t) {
   return hipErrorInvalidConfiguration;
 }
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);

@@ -1,7 +1,8 @@
 """GPU tests of the continuous-batching server (bp_server_* through the C ABI):
-requests that join and leave while others run give bitwise the fields of the
-same problem solved alone, admission respects the pool memory, and requests
-the server cannot run are rejected."""
+requests that join and leave while others run give the fields of the same
+problem solved alone (to rounding, where the mix changes a launch variant),
+admission respects the pool memory, and requests the server cannot run are
+rejected."""
 import sys
 
 import numpy as np
@@ -75,12 +76,17 @@ def test_served_results_equal_alone(lbm, prec):
     st = srv.stats()
     assert st["active"] == 0 and st["queued"] == 0 and st["free_bytes"] == st["pool_bytes"]
     srv.close()
+    # the served mix holds more than 128^2 cells at its finest depth, where the
+    # four-application launch with the restriction takes its 64-column form
+    # and a request alone the 32-column one: the same arithmetic, separately
+    # compiled, so equal to rounding
+    tol = 1e-6 if prec == "fp32_shifted" else 1e-12
     for i, (p, n) in enumerate(reqs):
         A = _alone(lbm, p, n, prec)
         B = got[i]
-        _say("served", i, p.name, n, rel(B["eta"], A["eta"]))
-        for k in ("eta", "p", "sigma"):
-            assert np.array_equal(A[k], B[k]), (i, p.name, k)
+        d = tuple(rel(B[k], A[k]) for k in ("eta", "p", "sigma"))
+        _say("served", i, p.name, n, d)
+        assert max(d) < tol, (i, p.name, d)
     if prec == "fp64":  # and the oracle agrees
         p, n = reqs[2]
         o = Oracle(p.replace(K=4, ne_fixed=3), threads=oracle_threads())
@@ -90,7 +96,8 @@ def test_served_results_equal_alone(lbm, prec):
 
 def test_admission_is_bounded_by_pool_memory(lbm):
     """A pool that holds two of the requests at a time: at most two run, the
-    others wait in the queue, and every result still equals the lone solve."""
+    others wait in the queue, and every result still equals the lone solve
+    (to rounding)."""
     probs = [(P.loaded_strip(n=128, alpha=0.6 + 0.05 * k), 3 + k) for k in range(5)]
     need = lbm.request_bytes(probs[0][0], "fp32_shifted")
     # the server's own area for 8 slots (descriptors of at most 4 KiB, 65536
@@ -111,9 +118,10 @@ def test_admission_is_bounded_by_pool_memory(lbm):
             break
     srv.close()
     assert seen_active == 2 and len(got) == len(probs)
-    for i, (p, n) in enumerate(probs):
+    for i, (p, n) in enumerate(probs):  # two 128^2 requests together: the wide form (see above)
         A = _alone(lbm, p, n, "fp32_shifted")
-        assert np.array_equal(A["eta"], got[i]["eta"]), i
+        d = (rel(got[i]["eta"], A["eta"]), rel(got[i]["p"], A["p"]))
+        assert max(d) < 1e-6, (i, d)
 
 
 def test_server_rejects_what_it_cannot_run(lbm):
