@@ -85,7 +85,8 @@ def step_bytes_per_cell(p, fp64: bool, shifted: bool):
     force = (9 + 2) * s + 2 * 8
     flow = 18 * s + 3 * 8
     extract = 8
-    rebase = ((17 + 3) + (ne - 1) * (8 + 2)) * 2 * s if shifted else 0.0  # step start; displacement per later cycle
+    # step start, then the new displacement reference written between cycles
+    rebase = ((17 + 3) * 2 + (ne - 1) * 2) * s if shifted else 0.0
     return ne * per_cycle + force + flow + extract + rebase
 
 

@@ -130,7 +130,7 @@ struct Layout {
   int64_t plane = 0;
   bool fdbl = true, shift = false;
   std::vector<LevelLay> lv;  // 1..L
-  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_pref;
+  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
   size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_elbc[4], off_ftype[4], off_flbc[4];
   int ntiles_fine = 0, ntiles_fine2 = 0;
   int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
@@ -188,6 +188,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.off_omf = take(lo.plane * 8);
   lo.off_Ft = take(2 * lo.plane * fs);
   lo.off_eref = lo.shift ? take(2 * lo.plane * fs) : SIZE_MAX;
+  lo.off_eref2 = lo.shift ? take(2 * lo.plane * fs) : SIZE_MAX;
   lo.off_pref = lo.shift ? take(lo.plane * fs) : SIZE_MAX;
   const size_t N = (size_t)p->nx * p->ny;
   lo.off_eta = take(2 * N * 8);
@@ -452,6 +453,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.pout = (double*)(base + lo.off_pout);
   d.Ft = base + lo.off_Ft;
   d.eref = lo.shift ? (void*)(base + lo.off_eref) : nullptr;
+  d.eref2 = lo.shift ? (void*)(base + lo.off_eref2) : nullptr;
   d.pref = lo.shift ? (void*)(base + lo.off_pref) : nullptr;
   d.eta = (double*)(base + lo.off_eta);
   d.sig = (double*)(base + lo.off_sig);
@@ -833,17 +835,39 @@ Op flow_op(Engine& E) {
 }
 
 // one time step.  Shifted storage re-bases at the start of the step and the
-// displacement again before every later V-cycle: the offsets then carry only
-// what one cycle changes.  Offsets that carry a whole step's change (early
-// steps move the solution by tens of per cent) lose in FP32 the stress moments,
+// displacement again between V-cycles: the offsets then carry only what one
+// cycle changes.  Offsets that carry a whole step's change (early steps move
+// the solution by tens of per cent) lose in FP32 the stress moments,
 // differences of neighbouring offsets, in proportion to the grid size.
+// Between cycles the re-base rides on the cycle's last finest-level launch
+// when that is a multi-application smoothing launch: it writes its output
+// re-based and the new reference to the other reference buffer, which the next
+// cycle reads.  Only an even number of boundaries is taken that way, so the
+// step ends on buffer eref; a remaining boundary takes the re-basing kernel.
 void build_step_ops(Engine& E, std::vector<Op>& ops) {
   ops.clear();
   if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
   ops.push_back(cell_op(E, OP_FORCE));
+  const int fusable = (E.shift && E.fuse && E.K >= 2) ? 2 * ((E.ne - 1) / 2) : 0;
+  int cur = 0;  // reference buffer of the cycle
   for (int j = 0; j < E.ne; ++j) {
-    if (E.shift && j > 0) ops.push_back(cell_op(E, OP_REBASE_EL));
+    if (E.shift && j > 0 && j > fusable) ops.push_back(cell_op(E, OP_REBASE_EL));
+    const size_t first = ops.size();
     add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse);
+    for (size_t i = first; i < ops.size(); ++i)
+      if (ops[i].kind == OP_SWEEP && ops[i].sw.depth == 0) ops[i].sw.eref_in = cur;
+    if (j + 1 <= fusable) {
+      // the trailing launches at depth 0 (one per storage group) are the last
+      // post-smoothing launch
+      size_t i = ops.size();
+      while (i > first && ops[i - 1].kind == OP_SWEEP && ops[i - 1].sw.depth == 0 &&
+             ops[i - 1].sw.in_sel == ops.back().sw.in_sel && ops[i - 1].apps == ops.back().apps)
+        --i;
+      // with fusion and K >= 2 the last launch of a smoothing run holds two or
+      // four applications (an odd remainder goes first)
+      for (size_t k = i; k < ops.size(); ++k) ops[k].sw.rebase_out = 1;
+      cur ^= 1;
+    }
   }
   if (E.ne > 0) {
     Op f = prob_op(E, OP_FINALIZE);

@@ -48,6 +48,7 @@ struct ProbD {
   const double* omf;          // per-cell flow relaxation rate or null
   void* Ft;                   // explicit force (2 planes)
   void* eref;                 // displacement reference (shifted storage) or null
+  void* eref2;                // its second buffer, written by a re-basing sweep
   void* pref;                 // pressure reference (shifted storage) or null
   double* eta;                // extraction output (2 dense planes)
   double* sig;                // extraction output (3 dense planes)
@@ -72,6 +73,9 @@ struct SweepL {
   int out_sel;    // 0: A, 1: B
   int prolong;    // add the coarse correction (coarser level's buffer A) to the input
   int partials;   // write norm partials (finest level)
+  int eref_in;    // shifted storage: the displacement reference is eref (0) or eref2 (1)
+  int rebase_out; // re-base the output on its displacement and write the new
+                  // reference to the other buffer (finest level, smoothing)
 };
 
 struct CellL {    // per-cell kernels over the finest level

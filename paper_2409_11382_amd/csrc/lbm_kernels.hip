@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
   const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
   const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
   Tc* rc = (MODE == kRestrict && l > 1) ? (Tc*)P.lv[l - 1].r : nullptr;
-  const T* eref = SHIFT ? (const T*)P.eref : nullptr;
+  const T* eref = SHIFT ? (const T*)(a.eref_in ? P.eref2 : P.eref) : nullptr;
   ElConst<T> k;
   k.om_s = T(P.om_s);
   k.om_d = T(P.om_d);
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
   const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
   Tc* rc = (RES && l > 1) ? (Tc*)P.lv[l - 1].r : nullptr;
-  const T* eref = SHIFT ? (const T*)P.eref : nullptr;
+  const T* eref = SHIFT ? (const T*)(a.eref_in ? P.eref2 : P.eref) : nullptr;
   ElConst<T> k;
   k.om_s = T(P.om_s);
   k.om_d = T(P.om_d);
@@ -580,8 +580,22 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
         }
         if (out) {
           const int64_t oidx = (int64_t)y * pitch + x;
+          T gn[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = omg * G[kk][q] + gam * gi[q];
+          for (int q = 0; q < 8; ++q) gn[q] = omg * G[kk][q] + gam * gi[q];
+          if (SHIFT && a.rebase_out) {
+            // the re-basing kernel's step on this output: its displacement
+            // moves into the reference, which goes to the other buffer
+            const T m10 = (gn[0] - gn[2]) + (gn[4] - gn[5]) + (gn[7] - gn[6]);
+            const T m01 = (gn[1] - gn[3]) + (gn[4] + gn[5]) - (gn[6] + gn[7]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) gn[q] -= el_geq<T>(q, m10, m01);
+            T* eo = (T*)(a.eref_in ? P.eref : P.eref2);
+            eo[oidx] = ex + m10;
+            eo[plane + oidx] = ey + m01;
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = gn[q];
         }
       } else {
 #pragma unroll

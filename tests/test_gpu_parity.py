@@ -239,6 +239,27 @@ def test_shifted_fp64_equals_plain_fp64(lbm):
     assert rel(B["eta"], A["eta"]) < 1e-13 and rel(B["p"], A["p"]) < 1e-12
 
 
+@pytest.mark.parametrize("K,ne", [(3, 4), (2, 2), (4, 5)])
+def test_shifted_rebase_schedules(lbm, K, ne):
+    """Shifted storage re-bases between V-cycles inside the cycle's last
+    finest-level launch for an even number of boundaries and with the
+    re-basing kernel for the rest: odd K (that launch is a pair after a single
+    application), even and odd N_E.  FP64 shifted equals plain FP64 to
+    rounding; FP32 shifted stays within 1e-5."""
+    p = mixed_walls(124, 68, seed=5).replace(K=K, ne_fixed=ne)
+    F = {}
+    for prec in ("fp64", "fp64_shifted", "fp32_shifted"):
+        s = lbm.Solver(p, prec)
+        s.step(4)
+        F[prec] = s.fields()
+        s.close()
+    A = F["fp64"]
+    d64 = (rel(F["fp64_shifted"]["eta"], A["eta"]), rel(F["fp64_shifted"]["p"], A["p"]))
+    d32 = (rel(F["fp32_shifted"]["eta"], A["eta"]), rel(F["fp32_shifted"]["p"], A["p"]))
+    _say("rebase schedule K", K, "N_E", ne, d64, d32)
+    assert max(d64) < 1e-12 and max(d32) < 1e-5
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32_shifted", 1e-5), ("fp32", 1e-2)])
 def test_fp32_paths_against_fp64_oracle(lbm, prec, tol):
     """FP32 with shifted storage must stay within 1e-5 of the FP64 oracle.  Plain
