@@ -198,7 +198,10 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
   // partials of the multi-application sweeps: as many tiles as the pair or
   // the quad geometry has, whichever the schedule uses on the finest level
-  lo.ntiles_fine2 = std::max(sweepn_tiles(p->nx, p->ny, lo.fdbl, 2), sweepn_tiles(p->nx, p->ny, lo.fdbl, 4));
+  lo.ntiles_fine2 = 0;
+  for (int A = 2; A <= 4; A += 2)
+    for (int alt = 0; alt < 2; ++alt)
+      lo.ntiles_fine2 = std::max(lo.ntiles_fine2, sweepn_tiles(p->nx, p->ny, lo.fdbl, A, lo.shift, alt && A == 2));
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
   // gather tables of the coarse tail's levels (8 words per cell, level 1 first)
@@ -226,8 +229,10 @@ size_t tile_entries_for(const Layout& lo) {
   for (int l = 1; l <= lo.L; ++l)
   {
     t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
-    for (int A = 2; A <= 5; ++A) t += (size_t)sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, A);
-    t += (size_t)sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, 5, true);  // either width of A = 5
+    const bool sh = lo.shift && l == lo.L;
+    for (int A = 2; A <= 5; ++A)  // either region
+      t += (size_t)std::max(sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, A, sh, false),
+                            sweepn_tiles(lo.lv[l].nx, lo.lv[l].ny, lo.lv[l].dbl, A, sh, A != 4));
   }
   t += (size_t)sweep_tiles(lo.nx, lo.ny);
   t += (size_t)cell_blocks(lo.nx, lo.ny) * 2;
@@ -427,7 +432,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.lv[l].ny = v.ny;
     d.lv[l].pitch = v.pitch;
     d.lv[l].tiles_x = sweep_tiles_x(v.nx);
-    for (int A = 2; A <= 5; ++A) d.lv[l].tiles_xn[A] = sweepn_tiles_x(v.nx, A);
+    for (int A = 2; A <= 5; ++A) d.lv[l].tiles_xn[A] = sweepn_tiles_x(v.nx, A, false);  // A = 5: set per depth
     d.lv[l].dbl = v.dbl ? 1 : 0;
     d.lv[l].plane = v.plane;
   }
@@ -525,7 +530,7 @@ struct Op {
   ProbL pl{};
   TailL tl{};
   int count = 0;          // tiles / problems
-  bool wide = false;      // four applications with restriction on 64-column regions
+  bool alt = false;       // multi-application launch: the alternative region
 };
 
 // tile-list key of a depth: full set or restriction set, one of three
@@ -558,12 +563,17 @@ constexpr int64_t kQuadMaxCells = 256 * 256;
 // the restriction takes the 64-column regions: 12 x 12 outputs of the narrow
 // region would need about two blocks per CU there
 constexpr int64_t kQuadNarrowResCells = 128 * 128;
+// a depth of at most this many cells in all takes pairs on tall regions (one
+// block per CU); larger ones keep two 8-wave blocks per CU, which hide each
+// other's barrier waits (BIOT_TALL_MAX_CELLS overrides the bound)
+constexpr int64_t kTallMaxCells = 512 * 512;
 struct DepthLists {
   int off[8][3] = {};
   int cnt[8][3] = {};
   bool quad = false;  // four applications per launch
   bool fres = false;  // restriction fused into the last pre-smoothing launch
   bool qwide = false; // its four-application form on 64-column regions
+  bool tall = false;  // pairs on tall regions
   int tail_off = 0, tail_cnt = 0;  // problems whose coarse tail starts here
 };
 
@@ -590,6 +600,7 @@ struct Engine {
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
   int64_t quad_max_cells = kQuadMaxCells;
+  int64_t tall_max_cells = kTallMaxCells;
   bool fuse_res = true;  // restriction fused into pre-smoothing on latency-bound depths
   double* host_pin = nullptr;
 };
@@ -622,6 +633,10 @@ void xcd_order(std::vector<int2>& tiles, size_t off) {
 // four applications per launch at depth d (FP64 shifted storage has no LDS
 // room for them on the finest level)
 bool quad_at(const Engine& E, int d) { return E.depth[d].quad && !(d == 0 && E.fdbl && E.shift); }
+// the alternative region for A applications per launch at depth d
+bool alt_at(const Engine& E, int d, int A) {
+  return (A == 2 || A == 3) ? E.depth[d].tall : (A == 5 && E.depth[d].qwide);
+}
 
 // write descriptors and tile lists for the current problem set
 bp_status engine_upload(Engine& E) {
@@ -643,9 +658,10 @@ bp_status engine_upload(Engine& E) {
     E.depth[d].quad = E.quad && depth_cells <= E.quad_max_cells;
     E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
     E.depth[d].qwide = depth_cells > kQuadNarrowResCells;
+    E.depth[d].tall = depth_cells <= E.tall_max_cells;
     for (size_t i = 0; i < np; ++i) {  // tiles along x of the level at this depth, by its A = 5 width
       const int l = E.probs[i]->L - d;
-      if (l >= 1) pd[i].lv[l].tiles_xn[5] = sweepn_tiles_x(E.probs[i]->lo.lv[l].nx, 5, E.depth[d].qwide);
+      if (l >= 1) pd[i].lv[l].tiles_xn[5] = sweepn_tiles_x(E.probs[i]->lo.lv[l].nx, 5, alt_at(E, d, 5));
     }
     for (int set = 0; set < 8; ++set)
       for (int g = 0; g < 3; ++g) {
@@ -658,7 +674,7 @@ bp_status engine_upload(Engine& E) {
           if ((set < 2 || set >= kSetFused) && td > 0 && d >= td) continue;  // inside the problem's coarse tail
           const LevelLay& v = P.lo.lv[l];
           const int A = set_apps(set);
-          const int nt = set >= kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, A, A == 5 && E.depth[d].qwide)
+          const int nt = set >= kSetFused ? sweepn_tiles(v.nx, v.ny, v.dbl, A, E.shift && d == 0, alt_at(E, d, A))
                                           : sweep_tiles(v.nx, v.ny);
           for (int t = 0; t < nt; ++t) tiles.push_back(make_int2((int)i, t));
         }
@@ -698,7 +714,8 @@ bp_status engine_upload(Engine& E) {
   // schedule uses there
   for (size_t i = 0; i < np; ++i) {
     const Prob& P = *E.probs[i];
-    pd[i].ntiles_fine2 = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, quad_at(E, 0) ? 4 : 2);
+    const int A0 = quad_at(E, 0) ? 4 : 2;
+    pd[i].ntiles_fine2 = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, A0, E.shift, alt_at(E, 0, A0));
   }
   std::vector<int> pids(np);
   for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
@@ -721,7 +738,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     Op o;
     o.kind = OP_SWEEP;
     o.apps = set_apps(set);
-    o.wide = o.apps == 5 && E.depth[d].qwide;
+    o.alt = alt_at(E, d, o.apps);
     o.mode = mode;
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
@@ -878,31 +895,22 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
   ops.push_back(prob_op(E, OP_ADVANCE));
 }
 
+// the multi-application launch of an op: applications per launch, then the
+// level (finest or coarse), shifted storage and the region (default or ALT)
+template <typename T, typename Tc, int APPS, bool RES, bool ALT>
+hipError_t sweepn_launch(const Op& o, hipStream_t s) {
+  if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false, APPS, RES, ALT>(o.sw, o.count, s);
+  return o.shift ? launch_tsweep2<T, Tc, true, true, APPS, RES, ALT>(o.sw, o.count, s)
+                 : launch_tsweep2<T, Tc, true, false, APPS, RES, ALT>(o.sw, o.count, s);
+}
+
 template <typename T, typename Tc>
 hipError_t sweep_launch(const Op& o, hipStream_t s) {
-  const bool fine = o.sw.depth == 0;
   switch (o.apps) {
-    case 5:
-      if (o.wide) {
-        if (!fine) return launch_tsweep2<T, Tc, false, false, 4, true, true>(o.sw, o.count, s);
-        return o.shift ? launch_tsweep2<T, Tc, true, true, 4, true, true>(o.sw, o.count, s)
-                       : launch_tsweep2<T, Tc, true, false, 4, true, true>(o.sw, o.count, s);
-      }
-      if (!fine) return launch_tsweep2<T, Tc, false, false, 4, true>(o.sw, o.count, s);
-      return o.shift ? launch_tsweep2<T, Tc, true, true, 4, true>(o.sw, o.count, s)
-                     : launch_tsweep2<T, Tc, true, false, 4, true>(o.sw, o.count, s);
-    case 4:
-      if (!fine) return launch_tsweep2<T, Tc, false, false, 4, false>(o.sw, o.count, s);
-      return o.shift ? launch_tsweep2<T, Tc, true, true, 4, false>(o.sw, o.count, s)
-                     : launch_tsweep2<T, Tc, true, false, 4, false>(o.sw, o.count, s);
-    case 3:
-      if (!fine) return launch_tsweep2<T, Tc, false, false, 2, true>(o.sw, o.count, s);
-      return o.shift ? launch_tsweep2<T, Tc, true, true, 2, true>(o.sw, o.count, s)
-                     : launch_tsweep2<T, Tc, true, false, 2, true>(o.sw, o.count, s);
-    case 2:
-      if (!fine) return launch_tsweep2<T, Tc, false, false, 2, false>(o.sw, o.count, s);
-      return o.shift ? launch_tsweep2<T, Tc, true, true, 2, false>(o.sw, o.count, s)
-                     : launch_tsweep2<T, Tc, true, false, 2, false>(o.sw, o.count, s);
+    case 5: return o.alt ? sweepn_launch<T, Tc, 4, true, true>(o, s) : sweepn_launch<T, Tc, 4, true, false>(o, s);
+    case 4: return sweepn_launch<T, Tc, 4, false, false>(o, s);
+    case 3: return o.alt ? sweepn_launch<T, Tc, 2, true, true>(o, s) : sweepn_launch<T, Tc, 2, true, false>(o, s);
+    case 2: return o.alt ? sweepn_launch<T, Tc, 2, false, true>(o, s) : sweepn_launch<T, Tc, 2, false, false>(o, s);
     default: break;
   }
   if (o.shift) {
@@ -1000,6 +1008,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_QUAD")) E.quad = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_QUAD_MAX_CELLS")) E.quad_max_cells = std::atoll(e);
+  if (const char* e = std::getenv("BIOT_TALL_MAX_CELLS")) E.tall_max_cells = std::atoll(e);
   if (const char* e = std::getenv("BIOT_NO_FUSE_RES")) E.fuse_res = (std::atoi(e) == 0);
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");

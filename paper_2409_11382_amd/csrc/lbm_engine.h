@@ -112,37 +112,56 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
 // restricted to the coarser level), 4 (four smoothing applications) and 5
 // (four, then the restricted residual).  A region is COLS x (WAVES NK 64/COLS)
 // cells with NK row indices per wave, each covering 64/COLS rows of COLS
-// cells; a tile has (COLS - 4 A) x (rows - 4 A) outputs.  Pairs take 64-cell
-// rows.  Four applications are used only on depths of few cells, where the
-// launch is bound by the dependent work of one block rather than by HBM: a
-// 32 x 32 region (16 x 16 outputs) spreads such a depth over about four times
-// as many compute units as a 64-column one, at twice its redundant halo work.
-// With the restriction (A = 5, halo 10) a 32 x 32 region keeps only 12 x 12
-// outputs; the WIDE form (64 x 32 region, 44 x 12 outputs) serves the larger
-// of the depths that take four applications.
-template <int A>
-__host__ __device__ constexpr int sweepn_waves() { return A <= 3 ? 8 : 16; }
-template <typename T, int A>
+// cells; a tile has (COLS - 4 A) x (rows - 4 A) outputs.  Each A has a
+// default region and, chosen per depth by the cells it covers in all, an
+// alternative (ALT):
+// - pairs, with or without the restriction, take 64-cell rows.  By default 8
+//   waves of 3 rows (FP64: 2): two blocks share a CU and hide each other's
+//   barrier waits, which is what bounds large grids.  ALT, for depths that
+//   fill the chip about once: tall regions of 32 rows (16 waves x 2) and 36
+//   rows (12 waves x 3), 24 output rows, one block per CU on a 512^2 level and
+//   less halo work; FP64 shifted storage lacks the LDS and keeps 8 waves.
+// - four applications are used only on depths of few cells, where the launch
+//   is bound by the dependent work of one block: a 32 x 32 region (16 x 16
+//   outputs) spreads such a depth over about four times as many compute units
+//   as a 64-column one.  With the restriction (A = 5, halo 10) the narrow
+//   region keeps only 12 x 12 outputs; ALT (64 x 32 region, 44 x 12 outputs)
+//   serves the larger of those depths.
+template <typename T, bool SHIFT, int A, bool ALT>
+__host__ __device__ constexpr int sweepn_waves() {
+  return A >= 4 ? 16 : ((!ALT || (sizeof(T) == 8 && SHIFT)) ? 8 : (A == 2 ? 16 : 12));
+}
+template <typename T, bool SHIFT, int A, bool ALT>
 __host__ __device__ constexpr int sweepn_rows() {
-  return A == 2 ? (sizeof(T) == 8 ? 2 : 3) : (A == 3 ? 3 : 1);
+  return A >= 4 ? ((A == 5 && ALT) ? 2 : 1)
+                : (A == 3 ? 3 : ((ALT && !(sizeof(T) == 8 && SHIFT)) ? 2 : (sizeof(T) == 8 ? 2 : 3)));
 }
-template <int A>
-__host__ __device__ constexpr int sweepn_cols() { return A <= 3 ? kWave : 32; }
-inline int sweepn_tile_x(int A, bool wide = false) {
-  return ((A <= 3 || wide) ? sweepn_cols<2>() : sweepn_cols<4>()) - 4 * A;
+template <int A, bool ALT>
+__host__ __device__ constexpr int sweepn_cols() { return (A <= 3 || ALT) ? kWave : 32; }
+template <typename T, bool SHIFT, int A, bool ALT>
+__host__ __device__ constexpr int sweepn_region_rows() {
+  return sweepn_waves<T, SHIFT, A, ALT>() * sweepn_rows<T, SHIFT, A, ALT>() * (kWave / sweepn_cols<A, ALT>());
 }
-inline int sweepn_tile_y(int A, bool dbl) {
+inline int sweepn_tile_x(int A, bool alt) { return ((A <= 3 || alt) ? kWave : 32) - 4 * A; }
+template <int A, bool ALT>
+inline int sweepn_region_rows_rt(bool dbl, bool shift) {
+  return dbl ? (shift ? sweepn_region_rows<double, true, A, ALT>() : sweepn_region_rows<double, false, A, ALT>())
+             : (shift ? sweepn_region_rows<float, true, A, ALT>() : sweepn_region_rows<float, false, A, ALT>());
+}
+// output rows
+inline int sweepn_tile_y(int A, bool dbl, bool shift, bool alt) {
   int rr = 0;
   switch (A) {
-    case 2: rr = sweepn_waves<2>() * (dbl ? sweepn_rows<double, 2>() : sweepn_rows<float, 2>()); break;
-    case 3: rr = sweepn_waves<3>() * sweepn_rows<float, 3>(); break;
-    case 4: rr = sweepn_waves<4>() * sweepn_rows<float, 4>() * (kWave / sweepn_cols<4>()); break;
-    default: rr = sweepn_waves<5>() * sweepn_rows<float, 5>() * (kWave / sweepn_cols<5>()); break;
+    case 2: rr = alt ? sweepn_region_rows_rt<2, true>(dbl, shift) : sweepn_region_rows_rt<2, false>(dbl, shift); break;
+    case 3: rr = alt ? sweepn_region_rows_rt<3, true>(dbl, shift) : sweepn_region_rows_rt<3, false>(dbl, shift); break;
+    case 4: rr = sweepn_region_rows_rt<4, false>(dbl, shift); break;
+    default: rr = alt ? sweepn_region_rows_rt<5, true>(dbl, shift) : sweepn_region_rows_rt<5, false>(dbl, shift); break;
   }
   return rr - 4 * A;
 }
-// WIDE (APPS = 4 with RES only): 64-column regions of 16 waves x 2 rows
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE = false>
+// ALT: the alternative region of the applications per launch (not for four
+// applications without the restriction)
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT = false>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
@@ -167,13 +186,13 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);
 
 inline int sweep_tiles_x(int nx) { return (nx + kTileX - 1) / kTileX; }
 inline int sweep_tiles(int nx, int ny) { return sweep_tiles_x(nx) * ((ny + kTileY - 1) / kTileY); }
-inline int sweepn_tiles_x(int nx, int apps, bool wide = false) {
-  return (nx + sweepn_tile_x(apps, wide) - 1) / sweepn_tile_x(apps, wide);
+inline int sweepn_tiles_x(int nx, int apps, bool alt) {
+  return (nx + sweepn_tile_x(apps, alt) - 1) / sweepn_tile_x(apps, alt);
 }
-// the row count of a WIDE region equals the narrow one's: 16 x 2 = 16 x 1 x 2
-inline int sweepn_tiles(int nx, int ny, bool dbl, int apps, bool wide = false) {
-  const int ty = sweepn_tile_y(apps, dbl);
-  return sweepn_tiles_x(nx, apps, wide) * ((ny + ty - 1) / ty);
+// shift: the level is the finest one of shifted storage
+inline int sweepn_tiles(int nx, int ny, bool dbl, int apps, bool shift, bool alt) {
+  const int ty = sweepn_tile_y(apps, dbl, shift, alt);
+  return sweepn_tiles_x(nx, apps, alt) * ((ny + ty - 1) / ty);
 }
 inline int cell_blocks(int nx, int ny) { return ((nx + kCellBX - 1) / kCellBX) * ((ny + kCellBY - 1) / kCellBY); }
 

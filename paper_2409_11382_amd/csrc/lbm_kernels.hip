@@ -298,14 +298,14 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 // the first ghost row/column of D must be restored by reflection (the loaded
 // ghosts were reflected copies; after an application they hold unused
 // values): columns by a lane permutation, rows through LDS.
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE>
-__global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(SweepL a) {
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT>
+__global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())) void k_tsweep2(SweepL a) {
   constexpr int A = APPS + (RES ? 1 : 0);
-  static_assert(!WIDE || A == 5, "the wide region serves four applications with the restriction");
-  constexpr int NW = sweepn_waves<A>();
-  constexpr int NK = WIDE ? 2 : sweepn_rows<T, A>();
+  static_assert(!ALT || A != 4, "four applications without the restriction have one region");
+  constexpr int NW = sweepn_waves<T, SHIFT, A, ALT>();
+  constexpr int NK = sweepn_rows<T, SHIFT, A, ALT>();
   constexpr int H = 2 * A;         // halo
-  constexpr int RX = WIDE ? kWave : sweepn_cols<A>();  // region columns
+  constexpr int RX = sweepn_cols<A, ALT>();  // region columns
   constexpr int S = kWave / RX;    // rows per wave and row index kk
   constexpr int RR = NW * NK * S;  // region rows
   constexpr int TY = RR - 2 * H;   // output rows
@@ -648,11 +648,11 @@ __global__ __launch_bounds__(kWave * sweepn_waves<APPS + RES>()) void k_tsweep2(
   }
 }
 
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool WIDE>
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT>
 hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, WIDE>), dim3(ntiles),
-                     dim3(kWave * sweepn_waves<APPS + (RES ? 1 : 0)>()), 0, s, a);
+  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT>), dim3(ntiles),
+                     dim3(kWave * sweepn_waves<T, SHIFT, APPS + (RES ? 1 : 0), ALT>()), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1533,23 +1533,25 @@ BIOT_SWEEP(float, float)
 BIOT_SWEEP(float, double)
 BIOT_SWEEP(double, double)
 #undef BIOT_SWEEP
+#define BIOT_SWEEPN_ALT(T, Tc, ALT)                                                                    \
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, false, ALT>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, false, ALT>(const SweepL&, int, hipStream_t); \
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, true, ALT>(const SweepL&, int, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, true, ALT>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, false, ALT>(const SweepL&, int, hipStream_t); \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, true, ALT>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true, ALT>(const SweepL&, int, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true, ALT>(const SweepL&, int, hipStream_t);
 #define BIOT_SWEEPN(T, Tc)                                                                            \
-  template hipError_t launch_tsweep2<T, Tc, true, true, 2, false>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 2, false>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, true, true, 2, true>(const SweepL&, int, hipStream_t);    \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 2, true>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 2, false>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 2, true>(const SweepL&, int, hipStream_t);   \
+  BIOT_SWEEPN_ALT(T, Tc, false)                                                                       \
+  BIOT_SWEEPN_ALT(T, Tc, true)                                                                        \
   template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true, true>(const SweepL&, int, hipStream_t); \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true, true>(const SweepL&, int, hipStream_t);
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, hipStream_t);
 BIOT_SWEEPN(float, float)
 BIOT_SWEEPN(float, double)
 BIOT_SWEEPN(double, double)
 #undef BIOT_SWEEPN
+#undef BIOT_SWEEPN_ALT
 template hipError_t launch_tsweep2<float, float, true, true, 4, false>(const SweepL&, int, hipStream_t);
 template hipError_t launch_tsweep2<float, float, true, true, 4, true>(const SweepL&, int, hipStream_t);
 template hipError_t launch_tsweep2<float, double, true, true, 4, false>(const SweepL&, int, hipStream_t);
