@@ -61,9 +61,12 @@ template <typename T> struct ElConst {
 // Post-collision populations from pre-collision u and the force F of this
 // application (Algorithm 2: moments, two half forces, Table 2 relaxation,
 // Table 3 back-transformation).  The moments 12, 21, f relax with rate 1, so
-// only m10, m01, m11, m_s, m_d of u enter.
+// only m10, m01, m11, m_s, m_d of u enter.  The result is multiplied by sc,
+// which the back-transformation's coefficients absorb (a smoother that blends
+// with weight gamma passes sc = gamma).
 template <typename T>
-__device__ __forceinline__ void el_collide(const T u[8], T Fx, T Fy, const ElConst<T>& c, T out[8]) {
+__device__ __forceinline__ void el_collide(const T u[8], T Fx, T Fy, const ElConst<T>& c, T out[8],
+                                           T sc = T(1)) {
   const T m10 = (u[0] - u[2]) + (u[4] - u[5]) + (u[7] - u[6]);
   const T m01 = (u[1] - u[3]) + (u[4] + u[5]) - (u[6] + u[7]);
   const T m11 = (u[4] - u[5]) + (u[6] - u[7]);
@@ -79,13 +82,14 @@ __device__ __forceinline__ void el_collide(const T u[8], T Fx, T Fy, const ElCon
   const T Dd = (T(1) - c.om_d) * md;      // m*d
   const T X = (T(1) - c.om_d) * m11;      // m*11
   const T Z = -c.beta22 * ms;             // m*22
-  const T a = T(0.5) * (A - P), b = T(0.5) * (B - Q);
-  const T cc = T(0.25) * S - T(0.5) * Z, dd = T(0.25) * Dd;
+  const T h2 = sc * T(0.5), h4 = sc * T(0.25);
+  const T a = h2 * (A - P), b = h2 * (B - Q);
+  const T cc = h4 * S - h2 * Z, dd = h4 * Dd;
   out[0] = (cc + dd) + a;
   out[2] = (cc + dd) - a;
   out[1] = (cc - dd) + b;
   out[3] = (cc - dd) - b;
-  const T e = T(0.25) * Z, p = T(0.25) * P, q = T(0.25) * Q, x = T(0.25) * X;
+  const T e = h4 * Z, p = h4 * P, q = h4 * Q, x = h4 * X;
   out[4] = (e + x) + (p + q);
   out[5] = (e - x) + (q - p);
   out[6] = (e + x) - (p + q);

@@ -403,12 +403,22 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
                    (!pery && ((ya <= 0 && yb >= 0) || (ya <= ny - 1 && yb >= ny - 1)));
 
   const T gam = k.gamma, omg = T(1) - k.gamma;
+  const double inv_gam = 1.0 / P.gamma;
   const int lm = clampi(col - 1, 0, RX - 1), lp = clampi(col + 1, 0, RX - 1);
   double acc_r = 0.0, acc_g = 0.0;
+  // shifted storage: the pull's correction per direction, the source's
+  // reference minus this cell's in the rest equilibrium of the population
+  // (el_geq); constant during the launch, formed in the first application
+  T Cr[SHIFT ? NK : 1][8];
 
 #pragma unroll
   for (int app = 0; app < A; ++app) {
     const int e = 2 * app;  // rows / columns [e, RR - e) hold a valid iterate
+    // smoothing applications stream gamma times the post-collision
+    // populations, so the blend (1 - gamma) g + gamma g_in is one FMA; the
+    // residual application streams them unscaled
+    const bool resid = RES && app == A - 1;
+    const T sc = resid ? T(1) : gam;
     // ---- D(g)
 #pragma unroll
     for (int kk = 0; kk < NK; ++kk) {
@@ -449,7 +459,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
 #pragma unroll
           for (int q = 0; q < 8; ++q) u[q] = G[kk][q] - Rv[kk][q];
         }
-        el_collide(u, fx, fy, k, s8);
+        el_collide(u, fx, fy, k, s8, sc);
 #pragma unroll
         for (int q = 0; q < 8; ++q) sS[q][j - 1][col] = s8[q];
       }
@@ -469,20 +479,22 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
       for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
       T ex = T(0), ey = T(0);
       if (SHIFT) {
-        // the source's reference minus this cell's, in the rest equilibrium
-        // of the population (el_geq), one LDS read per direction
         ex = Ex[kk];
         ey = Ey[kk];
-        const T sp = ex + ey, sm = ey - ex;
-        const T third = T(1.0 / 3.0), twelfth = T(1.0 / 12.0);
-        gi[0] += third * (sE[0][j][lc - 1] - ex);
-        gi[1] += third * (sE[1][j - 1][lc] - ey);
-        gi[2] -= third * (sE[0][j][lc + 1] - ex);
-        gi[3] -= third * (sE[1][j + 1][lc] - ey);
-        gi[4] += twelfth * (sE[2][j - 1][lc - 1] - sp);
-        gi[5] += twelfth * (sE[3][j - 1][lc + 1] - sm);
-        gi[6] -= twelfth * (sE[2][j + 1][lc + 1] - sp);
-        gi[7] -= twelfth * (sE[3][j + 1][lc - 1] - sm);
+        if (app == 0) {  // rows and columns pulled later are a subset
+          const T sp = ex + ey, sm = ey - ex;
+          const T third = T(1.0 / 3.0), twelfth = T(1.0 / 12.0);
+          Cr[kk][0] = third * (sE[0][j][lc - 1] - ex);
+          Cr[kk][1] = third * (sE[1][j - 1][lc] - ey);
+          Cr[kk][2] = -third * (sE[0][j][lc + 1] - ex);
+          Cr[kk][3] = -third * (sE[1][j + 1][lc] - ey);
+          Cr[kk][4] = twelfth * (sE[2][j - 1][lc - 1] - sp);
+          Cr[kk][5] = twelfth * (sE[3][j - 1][lc + 1] - sm);
+          Cr[kk][6] = -twelfth * (sE[2][j + 1][lc + 1] - sp);
+          Cr[kk][7] = -twelfth * (sE[3][j + 1][lc - 1] - sm);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) gi[q] += sc * Cr[kk][q];
       }
       bool wl = false, wr = false, wb = false, wt = false;
       int gy = 0;
@@ -509,7 +521,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
           if (ox && oy) {
             if (elx == kElSymmetry && ely == kElSymmetry) {
               v = sS[opp8(q)][c][lc];
-              if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+              if (SHIFT) v -= sc * (T(2) * el_geq<T>(q, ex, ey));
             } else {
               usex = ely == kElSymmetry;
               half = true;
@@ -518,14 +530,14 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
             usex = true;
             if (elx == kElSymmetry) {
               v = sS[mx8(q)][c - cy][lc];
-              if (SHIFT) v += el_geq<T>(mx8(q), sE[0][j - cy][lc], sE[1][j - cy][lc]) - el_geq<T>(q, ex, ey);
+              if (SHIFT) v += sc * (el_geq<T>(mx8(q), sE[0][j - cy][lc], sE[1][j - cy][lc]) - el_geq<T>(q, ex, ey));
             } else {
               half = true;
             }
           } else {
             if (ely == kElSymmetry) {
               v = sS[my8(q)][c][lc - cx];
-              if (SHIFT) v += el_geq<T>(my8(q), sE[0][j][lc - cx], sE[1][j][lc - cx]) - el_geq<T>(q, ex, ey);
+              if (SHIFT) v += sc * (el_geq<T>(my8(q), sE[0][j][lc - cx], sE[1][j][lc - cx]) - el_geq<T>(q, ex, ey));
             } else {
               half = true;
             }
@@ -536,11 +548,11 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
                                             : (cy > 0 ? P.elbc[kBottom] : P.elbc[kTop]))
                                     : nullptr;
             const int bidx = usex ? gy : gx;
-            const T add = bc ? T(bc[8 * bidx + q]) : T(0);
+            const T add = bc ? sc * T(bc[8 * bidx + q]) : T(0);
             const T o = sS[opp8(q)][c][lc];
             if (type == kElDirichlet) {
               v = o + add;
-              if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+              if (SHIFT) v -= sc * (T(2) * el_geq<T>(q, ex, ey));
             } else {
               v = -o + add;
             }
@@ -561,7 +573,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
         }
       } else if (RES && app == A - 2) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gam * gi[q];
+        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gi[q];
         if (out) {
           const int64_t oidx = (int64_t)y * pitch + x;
 #pragma unroll
@@ -571,7 +583,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
         if (a.partials && out) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            const double rho = double(G[kk][q]) - double(gi[q]);
+            const double rho = double(G[kk][q]) - double(gi[q]) * inv_gam;
             double gf = double(G[kk][q]);
             if (SHIFT) gf += double(el_geq<T>(q, ex, ey));
             acc_r += rho * rho;
@@ -582,7 +594,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
           const int64_t oidx = (int64_t)y * pitch + x;
           T gn[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) gn[q] = omg * G[kk][q] + gam * gi[q];
+          for (int q = 0; q < 8; ++q) gn[q] = omg * G[kk][q] + gi[q];
           if (SHIFT && a.rebase_out) {
             // the re-basing kernel's step on this output: its displacement
             // moves into the reference, which goes to the other buffer
@@ -599,7 +611,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
         }
       } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gam * gi[q];
+        for (int q = 0; q < 8; ++q) G[kk][q] = omg * G[kk][q] + gi[q];
       }
     }
   }
@@ -1187,12 +1199,13 @@ __device__ __forceinline__ void tail_relax(const ElConst<T>& k, int n, const Tai
     T u[8], s8[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) u[q] = G[c4][q] - R[c4][q];
-    el_collide(u, k.cstar * gx_, k.cstar * gy_, k, s8);
+    // a blending sweep streams gamma times the post-collision populations
+    el_collide(u, k.cstar * gx_, k.cstar * gy_, k, s8, blend ? k.gamma : T(1));
 #pragma unroll
     for (int q = 0; q < 8; ++q) sG[q * n + c] = s8[q];
   }
   __syncthreads();
-  const T gam = k.gamma, omg = T(1) - k.gamma;
+  const T omg = T(1) - k.gamma;
 #pragma unroll
   for (int c4 = 0; c4 < NC; ++c4) {
     const int c = t + kTailThreads * c4;
@@ -1202,7 +1215,7 @@ __device__ __forceinline__ void tail_relax(const ElConst<T>& k, int n, const Tai
       const uint32_t code = (q & 1) ? hi16(tb[c4].pl[q >> 1]) : lo16(tb[c4].pl[q >> 1]);
       const T v = sG[code & 0x7fffu];
       const T gi = (code & 0x8000u) ? -v : v;
-      G[c4][q] = blend ? omg * G[c4][q] + gam * gi : G[c4][q] - gi;
+      G[c4][q] = blend ? omg * G[c4][q] + gi : G[c4][q] - gi;
     }
   }
 }
