@@ -126,21 +126,24 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
 
 def dominant_kernel(solver, iters):
     """The finest-level smoothing launch of the step: two applications per
-    launch (k_tsweep2<float,float,fine,shift,2,no-restriction>).  Average
+    launch (k_tsweep2<float,float,fine,shift,2,no-restriction>), or four where
+    the tuning puts the finest depth on four-application launches.  Average
     device time of `iters` back-to-back launches (one captured graph, HIP
     events on the solver's stream) and its algorithmic bytes per launch: the
     populations read and written once, the explicit force and the displacement
     reference read once, 4 B each (80 B per cell)."""
+    apps = 4 if solver.tuning()["quad_max_cells"] >= solver.p.ncells else 2
     us, nbytes = solver.time_kernel(4, iters)
     achieved = nbytes / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_tsweep2<float,float,fine,shift,2 applications> (finest-level smoothing pair)",
+            "kernel": f"k_tsweep2<float,float,fine,shift,{apps} applications> (finest-level smoothing "
+                      f"{'pair' if apps == 2 else 'quad'})",
             "avg_us": round(us, 3), "bytes_per_launch": nbytes, "bytes_per_cell": 80,
-            "applications_per_launch": 2, "launches_timed": iters}
+            "applications_per_launch": apps, "launches_timed": iters}
 
 
-def batched(steps, warmup, count=256):
+def batched(steps, warmup, count=256, tune=True):
     """256 independent loaded-strip problems (grids 64..512, random material
     parameters) advanced together in FP32 with shifted populations."""
     from paper_2409_11382_amd import lbm
@@ -148,16 +151,17 @@ def batched(steps, warmup, count=256):
     probs = P.batch_problems(count=count, seed=1)
     cells = sum(p.ncells for p in probs)
     b = lbm.Batch(probs, "fp32_shifted")
+    tuning = b.autotune(steps=2) if tune else None
     wall, _ = time_steps(b, steps, warmup)
     per_step = wall / steps
-    out = {"problems": count, "cells": cells, "steps_timed": steps,
+    out = {"problems": count, "cells": cells, "steps_timed": steps, "tuning": tuning,
            "mlups": round(cells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * per_step, 4),
            "solves_per_s_300_steps": round(count / (300 * per_step), 3)}
     b.close()
     return out
 
 
-def heterogeneous(steps, warmup, n=2048):
+def heterogeneous(steps, warmup, n=2048, tune=True):
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
     p = P.heterogeneous_strip(n=n, ne_fixed=3, K=4)
@@ -165,8 +169,10 @@ def heterogeneous(steps, warmup, n=2048):
     fields = {}
     for prec in ("fp32_shifted", "fp64"):
         s = lbm.Solver(p, prec)
+        tuning = s.autotune(steps=3) if tune else None
         wall, _ = time_steps(s, steps, warmup)
-        res[prec] = {"mlups": round(p.ncells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * wall / steps, 4)}
+        res[prec] = {"mlups": round(p.ncells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * wall / steps, 4),
+                     "tuning": tuning}
         fields[prec] = s.fields()
         s.close()
     res["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(fields["fp32_shifted"][k], fields["fp64"][k])
@@ -175,7 +181,7 @@ def heterogeneous(steps, warmup, n=2048):
     return res
 
 
-def kernel_only(iters):
+def kernel_only(iters, tune=True):
     """Dominant kernel launches and a plain copy of COPY_BYTES bytes, for the
     kernel-trace and hardware-counter profiles."""
     import torch
@@ -183,6 +189,8 @@ def kernel_only(iters):
     from paper_2409_11382_amd import problem as P
     prob = P.loaded_strip(n=512, alpha=1.0, ne_fixed=3, K=4)
     s = lbm.Solver(prob, "fp32_shifted")
+    if tune:
+        s.autotune(steps=5)  # the launch shapes the benchmark times
     s.step(2)
     rl = dominant_kernel(s, iters)
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
@@ -210,6 +218,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=24)
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--kernel-only", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -224,16 +233,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lbm.load_library()
     if args.kernel_only:
-        kernel_only(args.kernel_iters)
+        kernel_only(args.kernel_iters, tune=not args.no_tune)
         return
     prob = P.loaded_strip(n=args.n, alpha=1.0, ne_fixed=3, K=4)
     N = prob.ncells
 
+    tune = not args.no_tune
     s32 = lbm.Solver(prob, "fp32_shifted")
+    # launch shapes chosen by the library's autotuner before the timed region
+    # (it leaves the solver in its initial state)
+    tuning = {"fp32_shifted": s32.autotune(steps=5) if tune else s32.tuning()}
     wall32, ev32 = time_steps(s32, args.steps, args.warmup)
     mlups32 = N * args.steps / wall32 / 1e6
     roof = dominant_kernel(s32, args.kernel_iters)
-    roof["traffic"] = measured_traffic()
+    # the counters were taken on the pair launch
+    roof["traffic"] = measured_traffic() if roof["applications_per_launch"] == 2 else None
     F32 = s32.fields()
     s32.close()
     b_step = step_bytes_per_cell(prob, fp64=False, shifted=True)
@@ -260,8 +274,10 @@ def main():
                           "achieved_GBs": round(mlups32 * 1e6 * b_step / 1e9, 1),
                           "frac": round(mlups32 * 1e6 * b_step / (HBM_PEAK_GBS * 1e9), 4)},
         "event_ms_per_step": round(1e3 * ev32 / args.steps, 5),
+        "tuning": tuning,
     }
     s64 = lbm.Solver(prob, "fp64")
+    tuning["fp64"] = s64.autotune(steps=5) if tune else s64.tuning()
     wall64, _ = time_steps(s64, args.steps, args.warmup)
     F64 = s64.fields()
     s64.close()
@@ -271,13 +287,14 @@ def main():
     out["fp32_speedup_over_fp64"] = round(wall64 / wall32, 3)
     if not args.no_extra:
         s05 = lbm.Solver(P.loaded_strip(n=args.n, alpha=0.5, ne_fixed=3, K=4), "fp32_shifted")
+        s05.set_tuning(tuning["fp32_shifted"])  # same sizes: the bounds found above
         w05, _ = time_steps(s05, args.steps // 5, 2)
         s05.close()
         out["alpha_0.5"] = {"value": round(N * (args.steps // 5) / w05 / 1e6, 3), "unit": "MLUPS"}
-        out["batched"] = batched(args.batch_steps, 2)
+        out["batched"] = batched(args.batch_steps, 2, tune=tune)
         from paper_2409_11382_amd import serve
         out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
-        out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2)
+        out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -161,6 +161,41 @@ bp_status bp_level_shape(const bp_solver *s, int32_t level, int32_t *nx, int32_t
 
 bp_status bp_stats(const bp_solver *s, bp_run_stats *st);
 
+/* ---- launch shapes and their autotuner.  The time-step schedule picks, per
+ * multigrid depth and by the cells the depth covers over all problems, how
+ * many smoothing applications one launch does and the region of a block
+ * (see the kernels' notes in lbm_engine.h).  These choices change the order
+ * of operations only: results agree to rounding (bitwise for the same
+ * choices).  Bounds are cell counts; a depth takes:
+ *   four applications per launch     if cells <= quad_max_cells
+ *   pairs on tall regions            if cells <= tall_max_cells
+ *   the restriction fused into the last pre-smoothing launch
+ *                                    if cells <= fuse_res_max_cells
+ *   four applications with the restriction on 32 x 32 regions
+ *                                    if cells <= quad_res_narrow_max_cells
+ *                                    (else on 64 x 32 regions)
+ * bp_autotune searches the bounds by coordinate descent: each bound in turn
+ * takes the value among five candidates whose time steps run fastest on this
+ * engine (HIP events, `steps` steps per candidate after one warm-up step; a
+ * candidate must beat the best so far by 2%), the others held.  It steps the
+ * problems while timing and re-initialises them at the end, so it must be
+ * called before the first step (else BP_ERR_STATE) and needs a fixed number
+ * of V-cycles (ne_fixed > 0, else BP_ERR_ARG).  *out (may be null) receives
+ * the chosen bounds and the measured milliseconds per step.  bp_set_tuning
+ * applies bounds (>= 0) at any time, for instance ones found earlier for the
+ * same sizes; bp_get_tuning reports the current ones (ms_per_step 0).  The
+ * server uses the default bounds. */
+typedef struct {
+  int64_t quad_max_cells;
+  int64_t tall_max_cells;
+  int64_t fuse_res_max_cells;
+  int64_t quad_res_narrow_max_cells;
+  double ms_per_step;
+} bp_tuning;
+bp_status bp_get_tuning(bp_solver *s, bp_tuning *out);
+bp_status bp_set_tuning(bp_solver *s, const bp_tuning *t);
+bp_status bp_autotune(bp_solver *s, int32_t steps, bp_tuning *out);
+
 /* Average device time (microseconds, HIP events on the solver's stream) of
  * `iters` back-to-back launches of one kernel on the current state, replayed
  * as one captured graph: which = 0 finest-level smoothing sweep, 1 finest-level
@@ -194,6 +229,10 @@ bp_status bp_batch_create(const bp_problem *probs, int32_t n, void *device_ws, s
 bp_status bp_batch_step(bp_batch *b, int32_t nsteps);
 bp_status bp_batch_get_fields(bp_batch *b, int32_t i, double *eta, double *p, double *sigma,
                               int32_t *step);
+/* the launch-shape tuning of a batch, as for a solver (bp_autotune) */
+bp_status bp_batch_get_tuning(bp_batch *b, bp_tuning *out);
+bp_status bp_batch_set_tuning(bp_batch *b, const bp_tuning *t);
+bp_status bp_batch_autotune(bp_batch *b, int32_t steps, bp_tuning *out);
 bp_status bp_batch_destroy(bp_batch *b);
 
 /* ---- serving: continuous batching of solve requests on one GPU.  The caller

@@ -599,8 +599,11 @@ struct Engine {
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
+  // launch-shape bounds (cells a depth covers in all); bp_tuning
   int64_t quad_max_cells = kQuadMaxCells;
   int64_t tall_max_cells = kTallMaxCells;
+  int64_t fres_max_cells = kFuseResCells;
+  int64_t qnarrow_max_cells = kQuadNarrowResCells;
   bool fuse_res = true;  // restriction fused into pre-smoothing on latency-bound depths
   double* host_pin = nullptr;
 };
@@ -656,8 +659,8 @@ bp_status engine_upload(Engine& E) {
       if (l >= 1 && !(td > 0 && d >= td)) depth_cells += (int64_t)P.lo.lv[l].nx * P.lo.lv[l].ny;
     }
     E.depth[d].quad = E.quad && depth_cells <= E.quad_max_cells;
-    E.depth[d].fres = E.fuse_res && depth_cells <= kFuseResCells;
-    E.depth[d].qwide = depth_cells > kQuadNarrowResCells;
+    E.depth[d].fres = E.fuse_res && depth_cells <= E.fres_max_cells;
+    E.depth[d].qwide = depth_cells > E.qnarrow_max_cells;
     E.depth[d].tall = depth_cells <= E.tall_max_cells;
     for (size_t i = 0; i < np; ++i) {  // tiles along x of the level at this depth, by its A = 5 width
       const int l = E.probs[i]->L - d;
@@ -1116,6 +1119,97 @@ bp_status init_fresh(Engine& E) {
   return BP_OK;
 }
 
+// ---------------------------------------------------------------- tuning
+void tuning_of(const Engine& E, bp_tuning* t) {
+  t->quad_max_cells = E.quad_max_cells;
+  t->tall_max_cells = E.tall_max_cells;
+  t->fuse_res_max_cells = E.fres_max_cells;
+  t->quad_res_narrow_max_cells = E.qnarrow_max_cells;
+  t->ms_per_step = 0.0;
+}
+
+bp_status apply_tuning(Engine& E, const bp_tuning* t) {
+  if (!t) return fail(BP_ERR_ARG, "null tuning");
+  if (t->quad_max_cells < 0 || t->tall_max_cells < 0 || t->fuse_res_max_cells < 0 ||
+      t->quad_res_narrow_max_cells < 0)
+    return fail(BP_ERR_ARG, "tuning bounds must be >= 0");
+  HIPCHK(hipStreamSynchronize(E.stream));
+  E.quad_max_cells = t->quad_max_cells;
+  E.tall_max_cells = t->tall_max_cells;
+  E.fres_max_cells = t->fuse_res_max_cells;
+  E.qnarrow_max_cells = t->quad_res_narrow_max_cells;
+  return engine_upload(E);  // new depth flags and tile lists; the step graph is rebuilt
+}
+
+// mean device time of n fixed-cycle steps after one warm-up step (which also
+// captures the step graph), by HIP events on the engine's stream
+bp_status time_steps(Engine& E, int n, double* ms) {
+  BPCHK(fixed_step(E));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(BP_ERR_DEVICE, "hipEventCreate failed");
+  }
+  bp_status rc = BP_OK;
+  if (hipEventRecord(e0, E.stream) != hipSuccess) rc = fail(BP_ERR_DEVICE, "hipEventRecord failed");
+  for (int k = 0; k < n && rc == BP_OK; ++k) rc = fixed_step(E);
+  float t = 0.f;
+  if (rc == BP_OK && (hipEventRecord(e1, E.stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                      hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    rc = fail(BP_ERR_DEVICE, "timing events failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = double(t) / n;
+  return rc;
+}
+
+// Coordinate descent over the four launch-shape bounds: each bound in turn
+// takes the candidate whose steps run fastest (by more than 2% over the best
+// so far), the others held.  Timing advances the problems, so the engine is
+// re-initialised at the end: only engines that have not stepped are tuned.
+bp_status autotune(Engine& E, int steps, bp_tuning* out) {
+  if (E.ne <= 0) return fail(BP_ERR_ARG, "autotuning needs a fixed number of V-cycles");
+  for (auto* P : E.probs)
+    if (P->step != 0) return fail(BP_ERR_STATE, "autotune runs before the first step");
+  if (steps < 1) steps = 1;
+  int64_t* knob[4] = {&E.quad_max_cells, &E.tall_max_cells, &E.fres_max_cells, &E.qnarrow_max_cells};
+  static const int64_t cand[4][5] = {{0, 64 * 64, 128 * 128, 256 * 256, 512 * 512},
+                                     {0, 256 * 256, 512 * 512, 1024 * 1024, 2048 * 2048},
+                                     {0, 256 * 256, 512 * 512, 1024 * 1024, 2048 * 2048},
+                                     {0, 64 * 64, 128 * 128, 256 * 256, 512 * 512}};
+  BPCHK(engine_upload(E));
+  double best = 0.0;
+  BPCHK(time_steps(E, steps, &best));
+  for (int k = 0; k < 4; ++k) {
+    const int64_t keep = *knob[k];
+    int64_t bestv = keep;
+    for (int c = 0; c < 5; ++c) {
+      if (cand[k][c] == keep) continue;
+      *knob[k] = cand[k][c];
+      BPCHK(engine_upload(E));
+      double ms = 0.0;
+      BPCHK(time_steps(E, steps, &ms));
+      if (ms < 0.98 * best) {
+        best = ms;
+        bestv = cand[k][c];
+      }
+    }
+    *knob[k] = bestv;
+  }
+  BPCHK(engine_upload(E));
+  BPCHK(init_states(E));
+  for (auto* P : E.probs) {
+    P->total_cycles = 0;
+    P->last_ne = 0;
+  }
+  if (out) {
+    tuning_of(E, out);
+    out->ms_per_step = best;
+  }
+  return BP_OK;
+}
+
 bp_status extract_fields(Engine& E) {
   std::vector<Op> ops{cell_op(E, OP_EXTRACT)};
   return run_ops(E, ops);
@@ -1525,6 +1619,27 @@ bp_status bp_stats(const bp_solver* s, bp_run_stats* st) {
   return BP_OK;
 }
 
+bp_status bp_get_tuning(bp_solver* s, bp_tuning* out) {
+  if (!s || !out) return fail(BP_ERR_ARG, "null argument");
+  tuning_of(s->E, out);
+  return BP_OK;
+}
+
+bp_status bp_set_tuning(bp_solver* s, const bp_tuning* t) {
+  if (!s) return fail(BP_ERR_ARG, "null solver");
+  return apply_tuning(s->E, t);
+}
+
+bp_status bp_autotune(bp_solver* s, int32_t steps, bp_tuning* out) {
+  if (!s) return fail(BP_ERR_ARG, "null solver");
+  if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
+  if (s->E.ne <= 0) return fail(BP_ERR_ARG, "autotuning needs a fixed number of V-cycles");
+  if (s->P.step != 0) return fail(BP_ERR_STATE, "autotune runs before the first step");
+  bp_status rc = autotune(s->E, steps, out);
+  if (rc != BP_OK) s->P.status = rc;  // a failure while stepping
+  return rc;
+}
+
 bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg_us, double* bytes) {
   if (!s || iters < 1 || !avg_us) return fail(BP_ERR_ARG, "bad arguments");
   Engine& E = s->E;
@@ -1681,6 +1796,22 @@ bp_status bp_batch_get_fields(bp_batch* b, int32_t i, double* eta, double* p, do
   if (!b || i < 0 || i >= (int)b->P.size()) return fail(BP_ERR_ARG, "bad batch index");
   BPCHK(extract_fields(b->E));
   return fields_of(b->E, b->P[i], eta, p, sigma, step);
+}
+
+bp_status bp_batch_get_tuning(bp_batch* b, bp_tuning* out) {
+  if (!b || !out) return fail(BP_ERR_ARG, "null argument");
+  tuning_of(b->E, out);
+  return BP_OK;
+}
+
+bp_status bp_batch_set_tuning(bp_batch* b, const bp_tuning* t) {
+  if (!b) return fail(BP_ERR_ARG, "null batch");
+  return apply_tuning(b->E, t);
+}
+
+bp_status bp_batch_autotune(bp_batch* b, int32_t steps, bp_tuning* out) {
+  if (!b) return fail(BP_ERR_ARG, "null batch");
+  return autotune(b->E, steps, out);
 }
 
 bp_status bp_batch_destroy(bp_batch* b) {

@@ -946,6 +946,10 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
     f1[i * V.plane + idx] = T(0);
   }
   const double Fx = P.fbody ? P.fbody[idx] : 0.0, Fy = P.fbody ? P.fbody[V.plane + idx] : 0.0;
+  // the force the extraction adds back (eta = m10 + F/2 = 0 at t = 0); every
+  // step recomputes it
+  ((T*)P.Ft)[idx] = T(Fx);
+  ((T*)P.Ft)[V.plane + idx] = T(Fy);
   // moments m10 = -F/2, m12 = -F/6 (x), m01 = -F/2, m21 = -F/6 (y); others 0
   const double A = -0.5 * Fx, B = -0.5 * Fy, Pm = -Fx / 6.0, Q = -Fy / 6.0;
   double g[8];

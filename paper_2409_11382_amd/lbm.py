@@ -42,6 +42,24 @@ class _Problem(C.Structure):
                 ("side", _Side * 4), ("prec", C.c_int32), ("pressure_gradient", C.c_int32)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("quad_max_cells", C.c_int64), ("tall_max_cells", C.c_int64),
+                ("fuse_res_max_cells", C.c_int64), ("quad_res_narrow_max_cells", C.c_int64),
+                ("ms_per_step", C.c_double)]
+
+
+def _tuning_dict(t):
+    return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+
+def _tuning_struct(d):
+    t = _Tuning()
+    for k, _ in _Tuning._fields_:
+        if k in d:
+            setattr(t, k, d[k])
+    return t
+
+
 class _Stats(C.Structure):
     _fields_ = [("step", C.c_int32), ("last_ne", C.c_int32), ("total_cycles", C.c_int64),
                 ("last_ratio", C.c_double), ("levels", C.c_int32), ("diverged", C.c_int32)]
@@ -73,6 +91,12 @@ def load_library():
             "bp_level_shape": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
             "bp_stats": [vp, C.POINTER(_Stats)],
             "bp_time_kernel": [vp, i32, i32, dp, dp],
+            "bp_get_tuning": [vp, C.POINTER(_Tuning)],
+            "bp_set_tuning": [vp, C.POINTER(_Tuning)],
+            "bp_autotune": [vp, i32, C.POINTER(_Tuning)],
+            "bp_batch_get_tuning": [vp, C.POINTER(_Tuning)],
+            "bp_batch_set_tuning": [vp, C.POINTER(_Tuning)],
+            "bp_batch_autotune": [vp, i32, C.POINTER(_Tuning)],
             "bp_device_copy": [vp, vp, C.c_size_t, vp],
             "bp_destroy": [vp],
             "bp_batch_workspace_bytes": [C.POINTER(_Problem), i32, C.POINTER(C.c_size_t)],
@@ -262,6 +286,24 @@ class Solver:
         _check(self._lib.bp_stats(self._h, C.byref(st)), "bp_stats")
         return {k: getattr(st, k) for k, _ in _Stats._fields_}
 
+    def autotune(self, steps=4):
+        """Choose the launch-shape bounds by timing (before the first step;
+        the state is re-initialised).  Returns the chosen bounds."""
+        t = _Tuning()
+        _check(self._lib.bp_autotune(self._h, int(steps), C.byref(t)), "bp_autotune")
+        return _tuning_dict(t)
+
+    def tuning(self):
+        t = _Tuning()
+        _check(self._lib.bp_get_tuning(self._h, C.byref(t)), "bp_get_tuning")
+        return _tuning_dict(t)
+
+    def set_tuning(self, bounds):
+        cur = self.tuning()
+        cur.update(bounds)
+        t = _tuning_struct(cur)
+        _check(self._lib.bp_set_tuning(self._h, C.byref(t)), "bp_set_tuning")
+
     def time_kernel(self, which, iters=20):
         us, by = C.c_double(0), C.c_double(0)
         _check(self._lib.bp_time_kernel(self._h, int(which), int(iters), C.byref(us), C.byref(by)),
@@ -323,6 +365,24 @@ class Batch:
 
     def step(self, n=1):
         _check(self._lib.bp_batch_step(self._h, int(n)), "bp_batch_step")
+
+    def autotune(self, steps=2):
+        """Choose the launch-shape bounds by timing (before the first step;
+        the problems are re-initialised).  Returns the chosen bounds."""
+        t = _Tuning()
+        _check(self._lib.bp_batch_autotune(self._h, int(steps), C.byref(t)), "bp_batch_autotune")
+        return _tuning_dict(t)
+
+    def tuning(self):
+        t = _Tuning()
+        _check(self._lib.bp_batch_get_tuning(self._h, C.byref(t)), "bp_batch_get_tuning")
+        return _tuning_dict(t)
+
+    def set_tuning(self, bounds):
+        cur = self.tuning()
+        cur.update(bounds)
+        t = _tuning_struct(cur)
+        _check(self._lib.bp_batch_set_tuning(self._h, C.byref(t)), "bp_batch_set_tuning")
 
     def fields(self, i):
         p = self.problems[i]
