@@ -161,6 +161,60 @@ def batched(steps, warmup, count=256, tune=True):
     return out
 
 
+def fp64_alone_ms_per_step(p, steps=5):
+    """Device time per step of one problem solved alone in plain FP64 (the
+    path the batched and served runs are compared with)."""
+    from paper_2409_11382_amd import lbm
+    s = lbm.Solver(p, "fp64")
+    _, ev = time_steps(s, steps, 2)
+    s.close()
+    return 1e3 * ev / steps
+
+
+def terzaghi(steps=200):
+    """Terzaghi 8 x 128 (3 levels), adaptive N_E to 1e-8, FP64: all 200 steps
+    from t = 0."""
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50)
+    s = lbm.Solver(p, "fp64")
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.fields()  # synchronises
+    wall = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    return {"steps": steps, "ms_per_step": round(1e3 * wall / steps, 4),
+            "mlups": round(p.ncells * steps / wall / 1e6, 4), "mean_ne": round(st["total_cycles"] / steps, 2),
+            "levels": st["levels"]}
+
+
+def speedups_over_fp64_alone(batch, rate, count):
+    """The batched and served FP32 runs against solving the same problems one
+    at a time in plain FP64 on the GPU (device time per step measured alone
+    for every grid size involved)."""
+    from paper_2409_11382_amd import problem as P
+    from paper_2409_11382_amd import serve
+    probs = P.batch_problems(count=batch["problems"], seed=1)
+    per_size = {}
+    for p in probs:
+        if p.nx not in per_size:
+            per_size[p.nx] = fp64_alone_ms_per_step(p)
+    seq_batch = sum(per_size[p.nx] for p in probs)  # ms per step of all problems in turn
+    out = {"batched": {"fp64_alone_ms_per_step_by_n": {str(k): round(v, 4) for k, v in sorted(per_size.items())},
+                       "speedup": round(seq_batch / batch["ms_per_step"], 3)}}
+    # served: every request arrives at once (saturated server) against the
+    # requests solved one after another in FP64
+    reqs = P.serving_requests(rate, count, seed=2)
+    seq = 0.0
+    for _, p, n in reqs:
+        seq += n * fp64_alone_ms_per_step(p, steps=3) / 1e3
+    sat = serve.simulate(rate=1e6, count=count, seed=2)
+    out["served"] = {"saturated": sat, "fp64_alone_sequential_s": round(seq, 3),
+                     "speedup": round(seq / sat["makespan_s"], 3)}
+    return out
+
+
 def heterogeneous(steps, warmup, n=2048, tune=True):
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
@@ -295,6 +349,9 @@ def main():
         from paper_2409_11382_amd import serve
         out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
+        out["terzaghi_8x128"] = terzaghi()
+        out["speedups_over_fp64_alone"] = speedups_over_fp64_alone(out["batched"], args.serve_rate,
+                                                                   args.serve_count)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
