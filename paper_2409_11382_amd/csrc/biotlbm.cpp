@@ -517,7 +517,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
 }
 
 // ---------------------------------------------------------------- engine
-enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_REBASE_FORCE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
 
 struct Op {
   OpKind kind;
@@ -866,8 +866,17 @@ Op flow_op(Engine& E) {
 // step ends on buffer eref; a remaining boundary takes the re-basing kernel.
 void build_step_ops(Engine& E, std::vector<Op>& ops) {
   ops.clear();
-  if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
-  ops.push_back(cell_op(E, OP_FORCE));
+  // the step-start re-base and the explicit force share a pass over the cells
+  // unless a problem takes the central pressure gradient, which reads the
+  // neighbours' populations that the re-base rewrites
+  bool central = false;
+  for (auto* P : E.probs) central = central || P->d.grad_central;
+  if (E.shift && !central) {
+    ops.push_back(cell_op(E, OP_REBASE_FORCE));
+  } else {
+    if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
+    ops.push_back(cell_op(E, OP_FORCE));
+  }
   const int fusable = (E.shift && E.fuse && E.K >= 2) ? 2 * ((E.ne - 1) / 2) : 0;
   int cur = 0;  // reference buffer of the cycle
   for (int j = 0; j < E.ne; ++j) {
@@ -889,13 +898,17 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
       cur ^= 1;
     }
   }
-  if (E.ne > 0) {
-    Op f = prob_op(E, OP_FINALIZE);
-    f.pl.fused = (E.fuse && E.K >= 2) ? 1 : 0;  // the last post-smoothing launch was a pair
-    ops.push_back(f);
-  }
   ops.push_back(flow_op(E));
-  ops.push_back(prob_op(E, OP_ADVANCE));
+  if (E.ne > 0) {
+    // the norms of the last post-smoothing launch (the flow step leaves them
+    // alone), then the step counter, in one launch
+    Op f = prob_op(E, OP_FINALIZE);
+    f.pl.fused = (E.fuse && E.K >= 2) ? 1 : 0;  // the last post-smoothing launch was multi-application
+    f.pl.advance = 1;
+    ops.push_back(f);
+  } else {
+    ops.push_back(prob_op(E, OP_ADVANCE));
+  }
 }
 
 // the multi-application launch of an op: applications per launch, then the
@@ -938,6 +951,8 @@ hipError_t run_op(const Engine& E, const Op& o) {
       if (o.cdbl) return sweep_launch<float, double>(o, s);
       return sweep_launch<float, float>(o, s);
     case OP_FORCE: return E.fdbl ? launch_force<double>(o.cl, o.count, s) : launch_force<float>(o.cl, o.count, s);
+    case OP_REBASE_FORCE:
+      return E.fdbl ? launch_rebase_force<double>(o.cl, o.count, s) : launch_rebase_force<float>(o.cl, o.count, s);
     case OP_REBASE:
     case OP_REBASE_EL: {
       const bool flow = o.kind == OP_REBASE;

@@ -87,6 +87,7 @@ struct ProbL {    // one block per problem
   const ProbD* probs;
   const int* pids;
   int fused;      // finalize: partials of the two-application sweep
+  int advance;    // finalize: also count the completed step (after the flow step)
 };
 
 // Coarse "tail" of the multigrid recursion: one 1024-thread workgroup per
@@ -171,6 +172,10 @@ template <typename T>
 hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
 hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s);
+// the step-start re-base followed by the explicit force with the first-moment
+// pressure gradient, in one pass over the cells
+template <typename T>
+hipError_t launch_rebase_force(const CellL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>
 hipError_t launch_extract(const CellL& a, int ntiles, hipStream_t s);
 

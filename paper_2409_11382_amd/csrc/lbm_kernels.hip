@@ -854,16 +854,12 @@ __device__ __forceinline__ CellPos cell_pos(const LevelD& V, int b) {
 
 // explicit force of the step: Ft = h^2 c0 f - alpha h grad p with the
 // first-moment gradient (eq. pressure:gradient) and the explicit part of the
-// centred source
+// centred source.  The source's gradient and the first-moment gradient need
+// the FP64 D fields of the 3 x 3 neighbourhood and the cell's own flow
+// populations (jx, jy: their first moments).
 template <typename T>
-__global__ __launch_bounds__(256) void k_force(CellL a) {
-  const int2 te = a.tiles[blockIdx.x];
-  const ProbD& P = a.probs[te.x];
-  const LevelD& V = P.lv[P.L];
-  const CellPos c = cell_pos(V, te.y);
-  if (!c.in) return;
-  const int n = *P.phase;
-  const T* f = (const T*)P.f[n & 1];
+__device__ __forceinline__ void force_first_moments(const ProbD& P, const LevelD& V, const CellPos& c, int n,
+                                                    double jx, double jy) {
   const double* D1 = P.D[(n + 2) % 3];
   const double* D2 = P.D[(n + 1) % 3];
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
@@ -882,25 +878,30 @@ __global__ __launch_bounds__(256) void k_force(CellL a) {
   double gx, gy;
   grad_c(st, gx, gy);
   const int64_t idx = (int64_t)c.y * V.pitch + c.x;
-  double px, py;  // gradient of p without its source part
-  if (P.grad_central) {
-    // central difference (eq. pressure:gradient:alternative) of the sum of the
-    // populations; shifted storage holds f - w p_ref, whose sum lacks p_ref
-    const T* pref = (const T*)P.pref;
-    double pv[3][3];
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
-        const int64_t k = (int64_t)ys * V.pitch + xs;
-        double sum = pref ? double(pref[k]) : 0.0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
-        pv[dy + 1][dx + 1] = sum;
-      }
-    grad_c(pv, px, py);
-  } else {
+  const double om = P.omf ? P.omf[idx] : P.omf_u;
+  const double px = -3.0 * om * jx, py = -3.0 * om * jy;
+  double Fx = -P.alpha * P.h * (px + 0.5 * gx);
+  double Fy = -P.alpha * P.h * (py + 0.5 * gy);
+  if (P.fbody) {
+    Fx += P.fbody[idx];
+    Fy += P.fbody[V.plane + idx];
+  }
+  T* Ft = (T*)P.Ft;
+  Ft[idx] = T(Fx);
+  Ft[V.plane + idx] = T(Fy);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_force(CellL a) {
+  const int2 te = a.tiles[blockIdx.x];
+  const ProbD& P = a.probs[te.x];
+  const LevelD& V = P.lv[P.L];
+  const CellPos c = cell_pos(V, te.y);
+  if (!c.in) return;
+  const int n = *P.phase;
+  const T* f = (const T*)P.f[n & 1];
+  const int64_t idx = (int64_t)c.y * V.pitch + c.x;
+  if (!P.grad_central) {
     // first moments of the populations (eq. pressure:gradient)
     double jx = 0.0, jy = 0.0;
 #pragma unroll
@@ -909,10 +910,43 @@ __global__ __launch_bounds__(256) void k_force(CellL a) {
       jx += v * cx9(i);
       jy += v * cy9(i);
     }
-    const double om = P.omf ? P.omf[idx] : P.omf_u;
-    px = -3.0 * om * jx;
-    py = -3.0 * om * jy;
+    force_first_moments<T>(P, V, c, n, jx, jy);
+    return;
   }
+  const double* D1 = P.D[(n + 2) % 3];
+  const double* D2 = P.D[(n + 1) % 3];
+  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
+  double st[3][3];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
+      const int64_t k = (int64_t)ys * V.pitch + xs;
+      const double d1 = D1[k], d2 = D2[k];
+      double v = -P.alpha_h * ((1.0 - P.r) * (d1 - d2) - P.r * d1);
+      if (P.src) v += P.src[k];
+      st[dy + 1][dx + 1] = v;
+    }
+  double gx, gy;
+  grad_c(st, gx, gy);
+  // central difference (eq. pressure:gradient:alternative) of the sum of the
+  // populations; shifted storage holds f - w p_ref, whose sum lacks p_ref
+  const T* pref = (const T*)P.pref;
+  double pv[3][3];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
+      const int64_t k = (int64_t)ys * V.pitch + xs;
+      double sum = pref ? double(pref[k]) : 0.0;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
+      pv[dy + 1][dx + 1] = sum;
+    }
+  double px, py;  // gradient of p without its source part
+  grad_c(pv, px, py);
   double Fx = -P.alpha * P.h * (px + 0.5 * gx);
   double Fy = -P.alpha * P.h * (py + 0.5 * gy);
   if (P.fbody) {
@@ -976,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 // re-basing of the shifted storage: move the per-cell references to the
 // current displacement (and, with FLOW, pressure) so the stored offsets stay
 // small
-template <typename T, bool FLOW>
+template <typename T, bool FLOW, bool FORCE = false>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
@@ -1004,9 +1038,20 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
     fv[i] = f[i * V.plane + idx];
     p += fv[i];
   }
+  double jx = 0.0, jy = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i * V.plane + idx] = fv[i] - T(w9(i)) * p;
+  for (int i = 0; i < 9; ++i) {
+    const T v = fv[i] - T(w9(i)) * p;
+    f[i * V.plane + idx] = v;
+    if (FORCE && i > 0) {
+      jx += double(v) * cx9(i);
+      jy += double(v) * cy9(i);
+    }
+  }
   ((T*)P.pref)[idx] += p;
+  // the step's explicit force from the re-based populations, as k_force
+  // (first-moment gradient only: it reads no neighbour's populations)
+  if (FORCE) force_first_moments<T>(P, V, c, *P.phase, jx, jy);
 }
 
 // displacement and stress of the current populations (eqs. displacement,
@@ -1073,6 +1118,12 @@ hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s) {
     hipLaunchKernelGGL((k_rebase<T, true>), dim3(ntiles), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_rebase<T, false>), dim3(ntiles), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_rebase_force(const CellL& a, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_rebase<T, true, true>), dim3(ntiles), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, bool SHIFT>
@@ -1491,6 +1542,7 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
     P.norm2[0] = sr[0];
     P.norm2[1] = sg[0];
     if (!isfinite(sr[0]) || !isfinite(sg[0])) P.flags[0] = 1;
+    if (a.advance) *P.phase += 1;
   }
 }
 
@@ -1599,6 +1651,8 @@ template hipError_t launch_init<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_init<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_rebase<float>(const CellL&, int, bool, hipStream_t);
 template hipError_t launch_rebase<double>(const CellL&, int, bool, hipStream_t);
+template hipError_t launch_rebase_force<float>(const CellL&, int, hipStream_t);
+template hipError_t launch_rebase_force<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<float, false>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<float, true>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<double, false>(const CellL&, int, hipStream_t);
