@@ -119,9 +119,18 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(problem.ncells * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} coupled steps of the same {problem.nx}x{problem.ny} workload after 1 untimed step, "
-                      f"FP64 C oracle, {threads} OpenMP threads"}
+    out = {"value": round(problem.ncells * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{n} coupled steps of the same {problem.nx}x{problem.ny} workload after 1 untimed step, "
+                     f"FP64 C oracle, {threads} OpenMP threads"}
+    if threads > 1:  # and on one core, a smaller sample
+        o1 = Oracle(problem, threads=1)
+        o1.step(1)
+        n1 = max(1, n // 4)
+        t0 = time.perf_counter()
+        o1.step(n1)
+        dt1 = time.perf_counter() - t0
+        out["one_core"] = {"value": round(problem.ncells * n1 / dt1 / 1e6, 4), "unit": "MLUPS", "steps": n1}
+    return out
 
 
 def dominant_kernel(solver, iters):
@@ -154,8 +163,10 @@ def batched(steps, warmup, count=256, tune=True):
     tuning = b.autotune(steps=2) if tune else None
     wall, _ = time_steps(b, steps, warmup)
     per_step = wall / steps
+    bytes_step = sum(step_bytes_per_cell(p, fp64=False, shifted=True) * p.ncells for p in probs)
     out = {"problems": count, "cells": cells, "steps_timed": steps, "tuning": tuning,
            "mlups": round(cells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * per_step, 4),
+           "hbm_frac_byte_model": round(bytes_step / per_step / (HBM_PEAK_GBS * 1e9), 4),
            "solves_per_s_300_steps": round(count / (300 * per_step), 3)}
     b.close()
     return out
@@ -226,6 +237,8 @@ def heterogeneous(steps, warmup, n=2048, tune=True):
         tuning = s.autotune(steps=3) if tune else None
         wall, _ = time_steps(s, steps, warmup)
         res[prec] = {"mlups": round(p.ncells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * wall / steps, 4),
+                     "hbm_frac_byte_model": round(step_bytes_per_cell(p, prec == "fp64", prec != "fp64") * p.ncells
+                                                  / (wall / steps) / (HBM_PEAK_GBS * 1e9), 4),
                      "tuning": tuning}
         fields[prec] = s.fields()
         s.close()
@@ -339,6 +352,19 @@ def main():
                    "ms_per_step": round(1e3 * wall64 / args.steps, 5)}
     out["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(F32[k], F64[k]) for k in ("eta", "p")}
     out["fp32_speedup_over_fp64"] = round(wall64 / wall32, 3)
+    # ablation: FP32 populations stored whole (no shift)
+    sp = lbm.Solver(prob, "fp32")
+    sp.set_tuning(tuning["fp32_shifted"])
+    wallp, _ = time_steps(sp, args.steps // 5, 2)
+    Fp = sp.fields()
+    sp.close()
+    s64b = lbm.Solver(prob, "fp64")
+    s64b.step(args.steps // 5 + 2)
+    F64b = s64b.fields()
+    s64b.close()
+    out["fp32_plain"] = {"value": round(N * (args.steps // 5) / wallp / 1e6, 3), "unit": "MLUPS",
+                         "steps": args.steps // 5 + 2,
+                         "rel_l2_vs_gpu_fp64": {k: _rel(Fp[k], F64b[k]) for k in ("eta", "p")}}
     if not args.no_extra:
         s05 = lbm.Solver(P.loaded_strip(n=args.n, alpha=0.5, ne_fixed=3, K=4), "fp32_shifted")
         s05.set_tuning(tuning["fp32_shifted"])  # same sizes: the bounds found above
@@ -348,6 +374,9 @@ def main():
         out["batched"] = batched(args.batch_steps, 2, tune=tune)
         from paper_2409_11382_amd import serve
         out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
+        keys = ("rate_per_s", "requests", "solves_per_s", "p50_latency_s", "p99_latency_s", "mlups", "peak_active")
+        out["serving_rate_sweep"] = [{k: v for k, v in serve.simulate(rate=r, count=12, seed=3).items() if k in keys}
+                                     for r in (2.0, 10.0, 20.0)]
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
         out["terzaghi_8x128"] = terzaghi()
         out["speedups_over_fp64_alone"] = speedups_over_fp64_alone(out["batched"], args.serve_rate,
