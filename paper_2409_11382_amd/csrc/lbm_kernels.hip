@@ -853,33 +853,58 @@ __device__ __forceinline__ CellPos cell_pos(const LevelD& V, int b) {
 }
 
 // explicit force of the step: Ft = h^2 c0 f - alpha h grad p with the
-// first-moment gradient (eq. pressure:gradient) and the explicit part of the
-// centred source.  The source's gradient and the first-moment gradient need
-// the FP64 D fields of the 3 x 3 neighbourhood and the cell's own flow
-// populations (jx, jy: their first moments).
-template <typename T>
-__device__ __forceinline__ void force_first_moments(const ProbD& P, const LevelD& V, const CellPos& c, int n,
-                                                    double jx, double jy) {
+// first-moment gradient (eq. pressure:gradient) or the central difference of
+// p (eq. pressure:gradient:alternative), and the explicit part of the centred
+// source.  A block of 64 x 4 cells first stages the inputs that the central
+// differences take from the 3 x 3 neighbourhood, for its 66 x 6 region: st,
+// the source's explicit part (FP64 D fields), and with CENTRAL the sum of the
+// populations plus the pressure reference.  Each is formed once per cell.
+constexpr int kFRX = kCellBX + 2, kFRY = kCellBY + 2;
+
+template <typename T, bool CENTRAL>
+__device__ __forceinline__ void force_stage(const ProbD& P, const LevelD& V, int b, int n, double (*sst)[kFRX],
+                                            double (*sp)[kFRX]) {
+  const int cbx = (V.nx + kCellBX - 1) / kCellBX;
+  const int x0 = (b % cbx) * kCellBX - 1, y0 = (b / cbx) * kCellBY - 1;
   const double* D1 = P.D[(n + 2) % 3];
   const double* D2 = P.D[(n + 1) % 3];
+  const T* f = (const T*)P.f[n & 1];
+  const T* pref = (const T*)P.pref;
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
-  double st[3][3];
+  for (int r = threadIdx.x; r < kFRX * kFRY; r += blockDim.x) {
+    const int rx = r % kFRX, ry = r / kFRX;
+    const int x = x0 + rx, y = y0 + ry;
+    if (x > V.nx || y > V.ny) continue;  // no cell of the grid reads farther
+    const int xs = ghost_map(x, V.nx, perx), ys = ghost_map(y, V.ny, pery);
+    const int64_t k = (int64_t)ys * V.pitch + xs;
+    const double d1 = D1[k], d2 = D2[k];
+    double v = -P.alpha_h * ((1.0 - P.r) * (d1 - d2) - P.r * d1);
+    if (P.src) v += P.src[k];
+    sst[ry][rx] = v;
+    if (CENTRAL) {
+      // shifted storage holds f - w p_ref, whose sum lacks p_ref
+      double sum = pref ? double(pref[k]) : 0.0;
 #pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
-      const int64_t k = (int64_t)ys * V.pitch + xs;
-      const double d1 = D1[k], d2 = D2[k];
-      double v = -P.alpha_h * ((1.0 - P.r) * (d1 - d2) - P.r * d1);
-      if (P.src) v += P.src[k];
-      st[dy + 1][dx + 1] = v;
+      for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
+      sp[ry][rx] = sum;
     }
-  double gx, gy;
-  grad_c(st, gx, gy);
+  }
+}
+
+// the 3 x 3 neighbourhood of this thread's cell in a staged plane
+__device__ __forceinline__ void force_gather(const double (*s)[kFRX], double v[3][3]) {
+  const int lx = threadIdx.x % kCellBX, ly = threadIdx.x / kCellBX;
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) v[dy][dx] = s[ly + dy][lx + dx];
+}
+
+// Ft from the gradients of the source part (gx, gy) and of p (px, py)
+template <typename T>
+__device__ __forceinline__ void force_write(const ProbD& P, const LevelD& V, const CellPos& c, double gx, double gy,
+                                            double px, double py) {
   const int64_t idx = (int64_t)c.y * V.pitch + c.x;
-  const double om = P.omf ? P.omf[idx] : P.omf_u;
-  const double px = -3.0 * om * jx, py = -3.0 * om * jy;
   double Fx = -P.alpha * P.h * (px + 0.5 * gx);
   double Fy = -P.alpha * P.h * (py + 0.5 * gy);
   if (P.fbody) {
@@ -891,71 +916,51 @@ __device__ __forceinline__ void force_first_moments(const ProbD& P, const LevelD
   Ft[V.plane + idx] = T(Fy);
 }
 
+// first-moment gradient (eq. pressure:gradient) from the first moments of the
+// cell's own populations
+__device__ __forceinline__ void force_moments(const ProbD& P, const LevelD& V, const CellPos& c, double jx,
+                                              double jy, double& px, double& py) {
+  const int64_t idx = (int64_t)c.y * V.pitch + c.x;
+  const double om = P.omf ? P.omf[idx] : P.omf_u;
+  px = -3.0 * om * jx;
+  py = -3.0 * om * jy;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_force(CellL a) {
+  __shared__ double sst[kFRY][kFRX];
+  __shared__ double sp[kFRY][kFRX];
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
   const LevelD& V = P.lv[P.L];
+  const int n = *P.phase;
+  const bool central = P.grad_central != 0;  // one problem per block
+  if (central)
+    force_stage<T, true>(P, V, te.y, n, sst, sp);
+  else
+    force_stage<T, false>(P, V, te.y, n, sst, sp);
+  __syncthreads();
   const CellPos c = cell_pos(V, te.y);
   if (!c.in) return;
-  const int n = *P.phase;
-  const T* f = (const T*)P.f[n & 1];
-  const int64_t idx = (int64_t)c.y * V.pitch + c.x;
-  if (!P.grad_central) {
-    // first moments of the populations (eq. pressure:gradient)
+  double v[3][3], gx, gy, px, py;
+  force_gather(sst, v);
+  grad_c(v, gx, gy);
+  if (central) {
+    force_gather(sp, v);
+    grad_c(v, px, py);  // gradient of p without its source part
+  } else {
+    const T* f = (const T*)P.f[n & 1];
+    const int64_t idx = (int64_t)c.y * V.pitch + c.x;
     double jx = 0.0, jy = 0.0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      const double v = double(f[i * V.plane + idx]);
-      jx += v * cx9(i);
-      jy += v * cy9(i);
+      const double fv = double(f[i * V.plane + idx]);
+      jx += fv * cx9(i);
+      jy += fv * cy9(i);
     }
-    force_first_moments<T>(P, V, c, n, jx, jy);
-    return;
+    force_moments(P, V, c, jx, jy, px, py);
   }
-  const double* D1 = P.D[(n + 2) % 3];
-  const double* D2 = P.D[(n + 1) % 3];
-  const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
-  double st[3][3];
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
-      const int64_t k = (int64_t)ys * V.pitch + xs;
-      const double d1 = D1[k], d2 = D2[k];
-      double v = -P.alpha_h * ((1.0 - P.r) * (d1 - d2) - P.r * d1);
-      if (P.src) v += P.src[k];
-      st[dy + 1][dx + 1] = v;
-    }
-  double gx, gy;
-  grad_c(st, gx, gy);
-  // central difference (eq. pressure:gradient:alternative) of the sum of the
-  // populations; shifted storage holds f - w p_ref, whose sum lacks p_ref
-  const T* pref = (const T*)P.pref;
-  double pv[3][3];
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int xs = ghost_map(c.x + dx, V.nx, perx), ys = ghost_map(c.y + dy, V.ny, pery);
-      const int64_t k = (int64_t)ys * V.pitch + xs;
-      double sum = pref ? double(pref[k]) : 0.0;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
-      pv[dy + 1][dx + 1] = sum;
-    }
-  double px, py;  // gradient of p without its source part
-  grad_c(pv, px, py);
-  double Fx = -P.alpha * P.h * (px + 0.5 * gx);
-  double Fy = -P.alpha * P.h * (py + 0.5 * gy);
-  if (P.fbody) {
-    Fx += P.fbody[idx];
-    Fy += P.fbody[V.plane + idx];
-  }
-  T* Ft = (T*)P.Ft;
-  Ft[idx] = T(Fx);
-  Ft[V.plane + idx] = T(Fy);
+  force_write<T>(P, V, c, gx, gy, px, py);
 }
 
 // initial conditions (eqs. ICs, ICs:moments with p = 0 and eta = 0 at t = 0)
@@ -1012,9 +1017,14 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 // small
 template <typename T, bool FLOW, bool FORCE = false>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
+  __shared__ double sst[FORCE ? kFRY : 1][kFRX];
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
   const LevelD& V = P.lv[P.L];
+  if (FORCE) {  // the force's source part (the re-base leaves the D fields alone)
+    force_stage<T, false>(P, V, te.y, *P.phase, sst, nullptr);
+    __syncthreads();
+  }
   const CellPos c = cell_pos(V, te.y);
   if (!c.in) return;
   const int64_t idx = (int64_t)c.y * V.pitch + c.x;
@@ -1051,7 +1061,13 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   ((T*)P.pref)[idx] += p;
   // the step's explicit force from the re-based populations, as k_force
   // (first-moment gradient only: it reads no neighbour's populations)
-  if (FORCE) force_first_moments<T>(P, V, c, *P.phase, jx, jy);
+  if (FORCE) {
+    double v3[3][3], gx, gy, px, py;
+    force_gather(sst, v3);
+    grad_c(v3, gx, gy);
+    force_moments(P, V, c, jx, jy, px, py);
+    force_write<T>(P, V, c, gx, gy, px, py);
+  }
 }
 
 // displacement and stress of the current populations (eqs. displacement,
