@@ -468,6 +468,8 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.norm2 = (double*)(base + lo.off_scal);
   d.phase = (int*)(base + lo.off_scal + 32);
   d.flags = (int*)(base + lo.off_scal + 40);
+  d.ad_ratio = (double*)(base + lo.off_scal + 16);
+  d.ad = (int*)(base + lo.off_scal + 48);
   d.ntiles_fine = lo.ntiles_fine;
   d.ttab = (uint32_t*)(base + lo.off_ttab);
   HIPCHK(launch_fill_zero(base, lo.total, st));
@@ -517,7 +519,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
 }
 
 // ---------------------------------------------------------------- engine
-enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_REBASE_FORCE, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_REBASE_FORCE, OP_AD_RESET, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
 
 struct Op {
   OpKind kind;
@@ -596,6 +598,14 @@ struct Engine {
   std::vector<Op> step_ops;
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
+  // adaptive schedule (single-problem engines): its fixed pieces, each an op
+  // list and, with a stream, a captured graph (AD_START: re-base, force and
+  // the stop flag's reset, AD_FIRST: the first V-cycle, AD_UNIT: re-base,
+  // measuring sweep, norms, stopping test and a later V-cycle, AD_END: flow
+  // step and counter, AD_UNITS: several units)
+  std::vector<Op> ad_ops[5];
+  hipGraphExec_t ad_graph[5] = {};
+  bool ad_valid = false;
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
@@ -730,6 +740,7 @@ bp_status engine_upload(Engine& E) {
     HIPCHK(hipMemcpyAsync(E.d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, E.stream));
   HIPCHK(hipStreamSynchronize(E.stream));
   E.graph_valid = false;
+  E.ad_valid = false;
   return BP_OK;
 }
 
@@ -786,14 +797,25 @@ int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, in
   return sel;
 }
 
+// launches add_smoothing issues for `count` applications
+int smoothing_launches(int count, bool quad, bool fuse) {
+  int n = 0;
+  while (count > 0) {
+    count -= (quad && count % 4 == 0) ? 4 : ((fuse && count % 2 == 0) ? 2 : 1);
+    ++n;
+  }
+  return n;
+}
+
 // Algorithm 4 at depth d for every problem that has a level there.  The
 // iterate of a level starts in buffer A (zero at coarse depths) and ends in A
 // after its 2K smoothing applications (the pre- and post-smoothing runs take
 // the same number of launches).  first_done: the first pre-smoothing sweep was
 // already issued (adaptive mode).  tail: problems whose coarse tail starts at
 // this depth run it in one launch (time-step schedule); without it every level
-// is swept by the tile kernels (inspection operations).  fuse: pairs of
-// smoothing applications per launch.
+// is swept by the tile kernels (inspection operations).  fuse: several
+// smoothing applications per launch (after a separate first sweep only where
+// the launch count keeps the iterate ending in A).
 void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true,
                 bool fuse = false) {
   if (d >= E.maxL) return;
@@ -811,14 +833,20 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
   bool here = false;
   for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
   if (!here) return;
-  fuse = fuse && tail && !first_done;
+  fuse = fuse && tail;
+  bool fuse_here = fuse;
+  if (first_done && fuse) {
+    const bool q = quad_at(E, d);
+    if ((1 + smoothing_launches(E.K - 1, q, true) + smoothing_launches(E.K, q, true)) % 2 != 0) fuse_here = false;
+  }
   bool deeper = false;
   for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   int sel = 0;
   bool restricted = false;
   if (first_done) {
     // the first pre-smoothing application (A -> B) was issued separately
-    sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, false);
+    sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, fuse_here, deeper && E.depth[d].fres,
+                        &restricted);
   } else {
     sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0, false, false, fuse, deeper && E.depth[d].fres, &restricted);
   }
@@ -826,7 +854,7 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
     if (!restricted) add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
     add_vcycle(E, ops, d + 1, false, false, tail, fuse);
   }
-  add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse);
+  add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse_here);
 }
 
 Op cell_op(Engine& E, OpKind k) {
@@ -967,6 +995,7 @@ hipError_t run_op(const Engine& E, const Op& o) {
       return E.shift ? launch_extract<float, true>(o.cl, o.count, s) : launch_extract<float, false>(o.cl, o.count, s);
     case OP_TAIL: return launch_tail(o.tl, o.count, E.fdbl, s);
     case OP_FINALIZE: return launch_finalize(o.pl, o.count, s);
+    case OP_AD_RESET: return launch_ad_reset(o.pl, s);
     case OP_ADVANCE: return launch_advance(o.pl, o.count, s);
   }
   return hipSuccess;
@@ -980,19 +1009,11 @@ bp_status run_ops(const Engine& E, const std::vector<Op>& ops) {
   return BP_OK;
 }
 
-bp_status build_graph(Engine& E) {
-  if (E.graph) {
-    (void)hipGraphExecDestroy(E.graph);
-    E.graph = nullptr;
-  }
-  E.graph_valid = false;
-  build_step_ops(E, E.step_ops);
-  if (!E.use_graph || !E.stream) {
-    E.graph_valid = true;
-    return BP_OK;
-  }
+// capture an op list on the engine's stream into an executable graph
+bp_status capture_ops(Engine& E, const std::vector<Op>& ops, hipGraphExec_t* out) {
+  *out = nullptr;
   HIPCHK(hipStreamBeginCapture(E.stream, hipStreamCaptureModeThreadLocal));
-  bp_status st = run_ops(E, E.step_ops);
+  bp_status st = run_ops(E, ops);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(E.stream, &g);
   if (st != BP_OK) {
@@ -1000,9 +1021,20 @@ bp_status build_graph(Engine& E) {
     return st;
   }
   if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&E.graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return BP_OK;
+}
+
+bp_status build_graph(Engine& E) {
+  if (E.graph) {
+    (void)hipGraphExecDestroy(E.graph);
+    E.graph = nullptr;
+  }
+  E.graph_valid = false;
+  build_step_ops(E, E.step_ops);
+  if (E.use_graph && E.stream) BPCHK(capture_ops(E, E.step_ops, &E.graph));
   E.graph_valid = true;
   return BP_OK;
 }
@@ -1037,6 +1069,10 @@ void engine_release(Engine& E) {
   (void)hipStreamSynchronize(E.stream);  // queued work may still read the pinned staging buffer
   if (E.graph) (void)hipGraphExecDestroy(E.graph);
   E.graph = nullptr;
+  for (auto& g : E.ad_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   if (E.host_pin) (void)hipHostFree(E.host_pin);
   E.host_pin = nullptr;
 }
@@ -1061,44 +1097,91 @@ bp_status fixed_step(Engine& E) {
 // adaptive number of V-cycles (single-problem engines): before V-cycle j+1
 // (j >= 1) the first smoothing sweep also measures ||g - S(g)|| and ||g||; the
 // cycle is abandoned (the sweep's output discarded) once the ratio reaches the
-// tolerance
+// tolerance or j reaches N_E,max.  The test runs on the device (in k_finalize)
+// and sets a stop flag that every launch of the following units checks, so
+// the host enqueues as many units (measuring sweep, test, cycle) as the last
+// step needed and reads the flag once; units past the stop do nothing.
+enum { AD_START, AD_FIRST, AD_UNIT, AD_END, AD_UNITS };
+constexpr int kAdUnits = 8;  // units per AD_UNITS graph (graph boundaries cost ~8 us each)
+
+void set_skip(std::vector<Op>& ops, size_t from, const int* flag) {
+  for (size_t k = from; k < ops.size(); ++k) {
+    Op& o = ops[k];
+    o.sw.skip = flag;
+    o.cl.skip = flag;
+    o.pl.skip = flag;
+    o.tl.skip = flag;
+  }
+}
+
+bp_status build_adaptive(Engine& E) {
+  Prob& P = *E.probs[0];
+  for (auto& g : E.ad_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  E.ad_valid = false;
+  for (auto& o : E.ad_ops) o.clear();
+  if (E.shift) E.ad_ops[AD_START].push_back(cell_op(E, OP_REBASE));
+  E.ad_ops[AD_START].push_back(cell_op(E, OP_FORCE));
+  E.ad_ops[AD_START].push_back(prob_op(E, OP_AD_RESET));
+  add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
+  std::vector<Op>& u = E.ad_ops[AD_UNIT];
+  if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
+  add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);
+  Op fin = prob_op(E, OP_FINALIZE);  // the norms, then the stopping test
+  fin.pl.decide = 1;
+  fin.pl.tol = P.ne_tol;
+  fin.pl.ne_max = P.ne_max;
+  u.push_back(fin);
+  set_skip(u, 0, P.d.ad);
+  const size_t c0 = u.size();
+  add_vcycle(E, u, 0, true, false, true, E.fuse);
+  set_skip(u, c0, P.d.ad);
+  E.ad_ops[AD_END].push_back(flow_op(E));
+  E.ad_ops[AD_END].push_back(prob_op(E, OP_ADVANCE));
+  for (int k = 0; k < kAdUnits; ++k) E.ad_ops[AD_UNITS].insert(E.ad_ops[AD_UNITS].end(), u.begin(), u.end());
+  if (E.use_graph && E.stream)
+    for (int k = 0; k < 5; ++k) BPCHK(capture_ops(E, E.ad_ops[k], &E.ad_graph[k]));
+  E.ad_valid = true;
+  return BP_OK;
+}
+
+bp_status run_adaptive(Engine& E, int k) {
+  if (E.ad_graph[k]) {
+    HIPCHK(hipGraphLaunch(E.ad_graph[k], E.stream));
+    return BP_OK;
+  }
+  return run_ops(E, E.ad_ops[k]);
+}
+
 bp_status adaptive_step(Engine& E) {
   Prob& P = *E.probs[0];
-  std::vector<Op> ops;
-  if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
-  ops.push_back(cell_op(E, OP_FORCE));
-  BPCHK(run_ops(E, ops));
-  int j = 0;
-  double ratio = -1.0;
+  if (!E.ad_valid) BPCHK(build_adaptive(E));
+  BPCHK(run_adaptive(E, AD_START));
+  BPCHK(run_adaptive(E, AD_FIRST));
+  // a step takes at most N_E,max units (the last one only tests)
+  const int cap = std::max(1, P.ne_max);
+  int batch = std::min(cap, P.last_ne > 0 ? P.last_ne : 8);
+  int issued = 0;
+  int* st = (int*)E.host_pin;
   for (;;) {
-    ops.clear();
-    if (j >= 1) {
-      if (E.shift) ops.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
-      add_sweeps(E, ops, 0, 0, kSmooth, 0, 1, 0, 1);
-      ops.push_back(prob_op(E, OP_FINALIZE));
-      BPCHK(run_ops(E, ops));
-      HIPCHK(hipMemcpyAsync(E.host_pin, P.d.norm2, 2 * sizeof(double), hipMemcpyDeviceToHost, E.stream));
-      HIPCHK(hipStreamSynchronize(E.stream));
-      const double nr = std::sqrt(E.host_pin[0]), ng = std::sqrt(E.host_pin[1]);
-      ratio = ng > 0 ? nr / ng : 0.0;
-      if (!std::isfinite(nr) || !std::isfinite(ng)) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
-      if (nr <= P.ne_tol * ng || j >= P.ne_max) break;
-      ops.clear();
-      add_vcycle(E, ops, 0, true, false);
-      BPCHK(run_ops(E, ops));
-    } else {
-      add_vcycle(E, ops, 0, false, false);
-      BPCHK(run_ops(E, ops));
-    }
-    ++j;
+    for (int k = 0; k + kAdUnits <= batch; k += kAdUnits) BPCHK(run_adaptive(E, AD_UNITS));
+    for (int k = 0; k < batch % kAdUnits; ++k) BPCHK(run_adaptive(E, AD_UNIT));
+    issued += batch;
+    HIPCHK(hipMemcpyAsync(st, P.d.ad, 2 * sizeof(int), hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipMemcpyAsync(E.host_pin + 1, P.d.ad_ratio, sizeof(double), hipMemcpyDeviceToHost, E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+    if (st[0] != 0) break;
+    if (issued >= cap) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
+    batch = std::min(4, cap - issued);
   }
+  if (st[0] == 2) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
+  const int j = st[1];
   P.last_ne = j;
-  P.last_ratio = ratio;
+  P.last_ratio = E.host_pin[1];
   P.total_cycles += j;
-  ops.clear();
-  ops.push_back(flow_op(E));
-  ops.push_back(prob_op(E, OP_ADVANCE));
-  BPCHK(run_ops(E, ops));
+  BPCHK(run_adaptive(E, AD_END));
   P.step += 1;
   return BP_OK;
 }

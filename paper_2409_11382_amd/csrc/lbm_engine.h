@@ -57,6 +57,8 @@ struct ProbD {
   double* norm2;              // finalized sums
   int* phase;                 // completed steps (device copy)
   int* flags;                 // [0] non-finite seen
+  int* ad;                    // adaptive cycles: [0] stop (1 converged or at N_E,max, 2 non-finite), [1] cycles done
+  double* ad_ratio;           // adaptive cycles: the last measured ||g - S(g)|| / ||g||
   double om_s, om_d, beta22, kD, cstar, gamma;
   double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
   int ntiles_fine;            // sweep tiles of the finest level
@@ -73,6 +75,7 @@ struct SweepL {
   int out_sel;    // 0: A, 1: B
   int prolong;    // add the coarse correction (coarser level's buffer A) to the input
   int partials;   // write norm partials (finest level)
+  const int* skip;  // when set and *skip != 0 the launch does nothing (adaptive cycles past their stop)
   int eref_in;    // shifted storage: the displacement reference is eref (0) or eref2 (1)
   int rebase_out; // re-base the output on its displacement and write the new
                   // reference to the other buffer (finest level, smoothing)
@@ -81,13 +84,18 @@ struct SweepL {
 struct CellL {    // per-cell kernels over the finest level
   const ProbD* probs;
   const int2* tiles;  // (problem, cell block)
+  const int* skip;    // as in SweepL
 };
 
 struct ProbL {    // one block per problem
   const ProbD* probs;
   const int* pids;
+  const int* skip;  // as in SweepL
   int fused;      // finalize: partials of the two-application sweep
   int advance;    // finalize: also count the completed step (after the flow step)
+  int decide;     // finalize: then the adaptive stopping test (tol, ne_max)
+  double tol;
+  int ne_max;
 };
 
 // Coarse "tail" of the multigrid recursion: one 1024-thread workgroup per
@@ -102,6 +110,7 @@ constexpr int kTailLdsBytes = 9 * kTailCellsF64 * 8;
 struct TailL {
   const ProbD* probs;
   const int* pids;
+  const int* skip;  // as in SweepL
   int depth;       // depth of the tail's top level
   int K;           // smoothing steps
 };
@@ -185,6 +194,9 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s);
 // elastic side types el[4]
 hipError_t launch_tail_tables(const int* el, int nx, int ny, uint32_t* out, hipStream_t s);
 hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s);
+// adaptive cycles on the device: reset the stop flag and count for a step
+// (the stopping test itself follows the norms in k_finalize)
+hipError_t launch_ad_reset(const ProbL& a, hipStream_t s);
 hipError_t launch_advance(const ProbL& a, int nprobs, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t s);

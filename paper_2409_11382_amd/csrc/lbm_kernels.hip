@@ -49,6 +49,7 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // ======================================================================
 template <typename T, typename Tc, int MODE, bool SHIFT>
 __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
   constexpr int TY = kTileY;     // output rows
   constexpr int RR = TY + 4;     // region rows (two halo rows each side)
   constexpr int CR = TY + 2;     // collision rows
@@ -300,6 +301,7 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 // values): columns by a lane permutation, rows through LDS.
 template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT>
 __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())) void k_tsweep2(SweepL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
   constexpr int A = APPS + (RES ? 1 : 0);
   static_assert(!ALT || A != 4, "four applications without the restriction have one region");
   constexpr int NW = sweepn_waves<T, SHIFT, A, ALT>();
@@ -1017,6 +1019,7 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 // small
 template <typename T, bool FLOW, bool FORCE = false>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
   __shared__ double sst[FORCE ? kFRY : 1][kFRX];
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
@@ -1506,6 +1509,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
   extern __shared__ char lds[];
   const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
   tail_run<T, double>(P, P.L - a.depth, a.K, lds);
@@ -1535,6 +1539,7 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
 // ======================================================================
 // fixed-order FP64 sum of the finest level's norm partials
 __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
   const ProbD& P = a.probs[a.pids[blockIdx.x]];
   __shared__ double sr[256], sg[256];
   double r = 0.0, g = 0.0;
@@ -1559,6 +1564,18 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
     P.norm2[1] = sg[0];
     if (!isfinite(sr[0]) || !isfinite(sg[0])) P.flags[0] = 1;
     if (a.advance) *P.phase += 1;
+    if (a.decide && !P.ad[0]) {
+      // the host's stopping test of the adaptive schedule, in the same FP64
+      // steps: stop, or count the cycle that follows
+      const double nr = sqrt(sr[0]), ng = sqrt(sg[0]);
+      P.ad_ratio[0] = ng > 0 ? nr / ng : 0.0;
+      if (!isfinite(nr) || !isfinite(ng))
+        P.ad[0] = 2;
+      else if (nr <= a.tol * ng || P.ad[1] >= a.ne_max)
+        P.ad[0] = 1;
+      else
+        P.ad[1] += 1;
+    }
   }
 }
 
@@ -1574,6 +1591,19 @@ __global__ __launch_bounds__(256) void k_copy(uint4* dst, const uint4* src, size
 __global__ __launch_bounds__(256) void k_zero(uint4* dst, size_t n16) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_ad_reset(ProbL a) {
+  if (threadIdx.x == 0) {
+    const ProbD& P = a.probs[a.pids[0]];
+    P.ad[0] = 0;
+    P.ad[1] = 1;  // the first cycle runs unconditionally
+  }
+}
+
+hipError_t launch_ad_reset(const ProbL& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_ad_reset, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const ProbL& a, int nprobs, hipStream_t s) {

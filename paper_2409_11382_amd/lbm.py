@@ -69,9 +69,16 @@ _lib = None
 
 
 def load_library():
-    """Load libbiotlbm.so; raises if it has not been built."""
+    """Load libbiotlbm.so; raises if it has not been built.
+
+    PyTorch is imported first: the library and PyTorch's bundled HIP runtime
+    share the soname libamdhip64.so.7, so whichever loads first is the one HIP
+    runtime of the process, and it must be the runtime PyTorch was built with
+    (the workspaces and streams come from PyTorch)."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2409_11382_amd/build.py")
         lib = C.CDLL(LIB_PATH)
