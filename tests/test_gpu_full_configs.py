@@ -217,7 +217,7 @@ def fp32_bar(n):
 
 def test_maximum_size_16384(lbm):
     """The largest grid the benchmark problem takes on one 288 GB GPU in both
-    precisions (16384^2 = 268 M cells: ~62 GB in FP32 shifted storage, ~107 GB
+    precisions (16384^2 = 268 M cells: ~81 GB in FP32 shifted storage, ~123 GB
     in FP64): properties that hold at any size, since the oracle cannot run
     here.  The fields are finite, mirror symmetric about x = 1/2 (eta_1 odd, eta_2
     and p even), and FP32 agrees with FP64 to the FP32 bar of this size."""

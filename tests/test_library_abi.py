@@ -48,6 +48,34 @@ def test_workspace_size_and_validation_are_host_only():
         L.workspace_bytes(p.replace(sides=sides))
 
 
+def test_degenerate_problems_are_rejected_on_the_host():
+    """Empty grids, shapes the hierarchy cannot coarsen, coarsest levels
+    below two cells in a walled direction, non-finite or out-of-range
+    parameters, an adaptive mode without a tolerance, an unknown gradient
+    variant, and empty or mixed batches."""
+    nan = float("nan")
+    base = P.loaded_strip(n=64)
+    bad = [dict(nx=0), dict(ny=0), dict(dt=0.0), dict(dx=-1.0), dict(alpha=nan), dict(mu=nan),
+           dict(gamma=1.5), dict(ne_fixed=0, ne_tol=0.0), dict(ne_fixed=0, ne_tol=1e-6, ne_max=0),
+           dict(pressure_gradient=2), dict(levels=7),          # 64 / 2^6 = 1 cell on the coarsest level
+           dict(nx=63, levels=2)]                              # odd width cannot coarsen
+    for kw in bad:
+        with pytest.raises(L.BiotError) as ei:
+            L.workspace_bytes(base.replace(**kw), "fp64")
+        assert ei.value.code in (L.BP_ERR_ARG, L.BP_ERR_SHAPE), kw
+    # the largest grid of the tests is accepted and sized without overflow
+    big = L.workspace_bytes(P.loaded_strip(n=16384), "fp32_shifted")
+    assert 75e9 < big < 85e9  # about 300 B per cell
+    lib = L.load_library()
+    n = C.c_size_t(0)
+    assert lib.bp_batch_workspace_bytes(None, 0, C.byref(n)) == L.BP_ERR_ARG
+    pa, ka = L.marshal_problem(base, "fp32_shifted")
+    pb, kb = L.marshal_problem(base, "fp64")
+    arr = (L._Problem * 2)(pa, pb)
+    assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # one precision per batch
+    del ka, kb
+
+
 def test_last_error_message():
     lib = L.load_library()
     with pytest.raises(L.BiotError):
