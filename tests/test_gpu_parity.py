@@ -187,6 +187,47 @@ def test_central_pressure_gradient_variant(lbm):
     _say("central gradient, strip fp32 shifted", worst)
 
 
+def _adaptive_run(lbm, p, prec, nsteps):
+    s = lbm.Solver(p, prec)
+    ne = []
+    for _ in range(nsteps):
+        s.step(1)
+        ne.append(s.stats()["last_ne"])
+    F = s.fields()
+    s.close()
+    return ne, F
+
+
+def test_adaptive_cycles_shifted_and_large(lbm):
+    """The adaptive schedule where the finest level of 512^2 runs single
+    applications after the measuring sweep and the coarser depths fused
+    launches (the oracle replays the GPU's counts), and in shifted storage:
+    FP64 shifted takes the plain FP64 counts and fields, FP32 shifted stays
+    within 1e-5 of the oracle replaying its counts."""
+    p = P.loaded_strip(n=512, alpha=1.0, ne_fixed=0, ne_tol=1e-6, ne_max=20)
+    ne, A = _adaptive_run(lbm, p, "fp64", 2)
+    _say("adaptive 512 fp64 N_E", ne)
+    o = Oracle(p, threads=oracle_threads(), history=2)
+    o.set_ne_schedule(np.array(ne, dtype=np.int32))
+    o.step(2)
+    B = o.fields()
+    assert rel(A["eta"], B["eta"]) < STEP_TOL and rel(A["p"], B["p"]) < STEP_TOL
+    q = mixed_walls(124, 68, seed=3).replace(ne_fixed=0, ne_tol=1e-7, ne_max=30)
+    n64, F64 = _adaptive_run(lbm, q, "fp64", 6)
+    n64s, F64s = _adaptive_run(lbm, q, "fp64_shifted", 6)
+    _say("adaptive mixed N_E fp64", n64, "fp64 shifted", n64s)
+    assert n64 == n64s
+    assert rel(F64s["eta"], F64["eta"]) < 1e-12 and rel(F64s["p"], F64["p"]) < 1e-12
+    n32, F32 = _adaptive_run(lbm, q, "fp32_shifted", 6)
+    o = Oracle(q, threads=oracle_threads(), history=6)
+    o.set_ne_schedule(np.array(n32, dtype=np.int32))
+    o.step(6)
+    C = o.fields()
+    e = (rel(F32["eta"], C["eta"]), rel(F32["p"], C["p"]))
+    _say("adaptive mixed fp32 shifted N_E", n32, e)
+    assert max(e) < 1e-5
+
+
 def test_adaptive_cycles_follow_oracle(lbm):
     """Configuration 1 (Terzaghi 8x128, tolerance 1e-8, at most 50 cycles): the
     GPU's V-cycle counts are replayed by the oracle; the oracle's own adaptive
