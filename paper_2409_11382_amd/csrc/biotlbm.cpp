@@ -117,6 +117,10 @@ bp_status validate(const bp_problem* p) {
 }
 
 // ---------------------------------------------------------------- layout
+// shifted storage keeps its references in FP64 above this many finest cells
+// (BIOT_REF64_CELLS sets another bound, BIOT_REF64 = 0 / 1 overrides either
+// for FP32 populations)
+constexpr int64_t kRef64Cells = 4096 * 4096;
 struct LevelLay {
   int nx = 0, ny = 0, pitch = 0;
   int64_t plane = 0;
@@ -128,7 +132,7 @@ struct LevelLay {
 struct Layout {
   int L = 1, nx = 0, ny = 0, pitch = 0;
   int64_t plane = 0;
-  bool fdbl = true, shift = false;
+  bool fdbl = true, shift = false, ref64 = true;
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
   size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_elbc[4], off_ftype[4], off_flbc[4];
@@ -187,9 +191,17 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.off_src = take(lo.plane * 8);
   lo.off_omf = take(lo.plane * 8);
   lo.off_Ft = take(2 * lo.plane * fs);
-  lo.off_eref = lo.shift ? take(2 * lo.plane * fs) : SIZE_MAX;
-  lo.off_eref2 = lo.shift ? take(2 * lo.plane * fs) : SIZE_MAX;
-  lo.off_pref = lo.shift ? take(lo.plane * fs) : SIZE_MAX;
+  // references of shifted storage: FP64 with FP64 populations and on grids
+  // above kRef64Cells cells (an FP32 reference's neighbour differences keep
+  // about eps_32 * N relative accuracy), else FP32
+  int64_t ref64_cells = kRef64Cells;
+  if (const char* e = std::getenv("BIOT_REF64_CELLS")) ref64_cells = std::atoll(e);
+  lo.ref64 = lo.fdbl || (int64_t)p->nx * p->ny > ref64_cells;
+  if (const char* e = std::getenv("BIOT_REF64")) lo.ref64 = lo.fdbl || std::atoi(e) != 0;
+  const size_t rs = lo.ref64 ? 8 : 4;
+  lo.off_eref = lo.shift ? take(2 * lo.plane * rs) : SIZE_MAX;
+  lo.off_eref2 = lo.shift ? take(2 * lo.plane * rs) : SIZE_MAX;
+  lo.off_pref = lo.shift ? take(lo.plane * rs) : SIZE_MAX;
   const size_t N = (size_t)p->nx * p->ny;
   lo.off_eta = take(2 * N * 8);
   lo.off_sig = take(3 * N * 8);
@@ -459,6 +471,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.Ft = base + lo.off_Ft;
   d.eref = lo.shift ? (void*)(base + lo.off_eref) : nullptr;
   d.eref2 = lo.shift ? (void*)(base + lo.off_eref2) : nullptr;
+  d.ref64 = lo.ref64 ? 1 : 0;
   d.pref = lo.shift ? (void*)(base + lo.off_pref) : nullptr;
   d.eta = (double*)(base + lo.off_eta);
   d.sig = (double*)(base + lo.off_sig);
@@ -527,6 +540,7 @@ struct Op {
   int apps = 1;           // smoothing applications per launch
   int tdbl = 0, cdbl = 0; // sweep storage types (level, coarser level)
   bool shift = false;
+  bool ref64 = false;     // shifted storage: a problem of the launch keeps FP64 references
   SweepL sw{};
   CellL cl{};
   ProbL pl{};
@@ -582,6 +596,7 @@ struct DepthLists {
 struct Engine {
   hipStream_t stream = nullptr;
   bool fdbl = true, shift = false;
+  bool ref64 = false;  // shifted storage: some problem keeps FP64 references
   int K = 4, ne = 3, maxL = 1;
   std::vector<Prob*> probs;
   // engine area (device): descriptors, tile lists, problem ids
@@ -658,7 +673,11 @@ bp_status engine_upload(Engine& E) {
   std::vector<ProbD> pd(np);
   for (size_t i = 0; i < np; ++i) pd[i] = E.probs[i]->d;
   E.maxL = 1;
-  for (auto* P : E.probs) E.maxL = std::max(E.maxL, P->L);
+  E.ref64 = false;
+  for (auto* P : E.probs) {
+    E.maxL = std::max(E.maxL, P->L);
+    E.ref64 = E.ref64 || (P->lo.shift && P->lo.ref64);
+  }
   std::vector<int2> tiles;
   E.depth.assign(E.maxL, DepthLists());
   for (int d = 0; d < E.maxL; ++d) {
@@ -757,6 +776,7 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     o.tdbl = g == 2;
     o.cdbl = g >= 1;
     o.shift = E.shift && d == 0;
+    o.ref64 = o.shift && E.ref64;
     o.sw.probs = E.d_probs;
     o.sw.tiles = E.d_tiles + E.depth[d].off[set][g];
     o.sw.depth = d;
@@ -944,7 +964,7 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
 template <typename T, typename Tc, int APPS, bool RES, bool ALT>
 hipError_t sweepn_launch(const Op& o, hipStream_t s) {
   if (o.sw.depth != 0) return launch_tsweep2<T, Tc, false, false, APPS, RES, ALT>(o.sw, o.count, s);
-  return o.shift ? launch_tsweep2<T, Tc, true, true, APPS, RES, ALT>(o.sw, o.count, s)
+  return o.shift ? launch_tsweep2<T, Tc, true, true, APPS, RES, ALT>(o.sw, o.count, o.ref64, s)
                  : launch_tsweep2<T, Tc, true, false, APPS, RES, ALT>(o.sw, o.count, s);
 }
 
@@ -1577,8 +1597,8 @@ bp_status bp_get_state(bp_solver* s, double* f, double* g, double* D1, double* D
   if (P.lo.shift) {
     pr.resize(N);
     er.resize(2 * N);
-    BPCHK(down(st, P.lo.fdbl, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
-    BPCHK(down(st, P.lo.fdbl, P.d.eref, nx, ny, P.lo.pitch, P.lo.plane, er.data(), 2));
+    BPCHK(down(st, P.lo.ref64, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
+    BPCHK(down(st, P.lo.ref64, P.d.eref, nx, ny, P.lo.pitch, P.lo.plane, er.data(), 2));
   }
   if (f) {
     BPCHK(down(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
@@ -1612,8 +1632,8 @@ bp_status bp_set_state(bp_solver* s, const double* f, const double* g, const dou
   int ph[2] = {n, 0};  // phase, flags
   HIPCHK(hipMemcpyAsync(P.d.phase, ph, 2 * sizeof(int), hipMemcpyHostToDevice, st));
   if (P.lo.shift) {  // references to zero: stored offsets are the full populations
-    HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
-    HIPCHK(launch_fill_zero(P.d.pref, align_up(P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+    HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
+    HIPCHK(launch_fill_zero(P.d.pref, align_up(P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
   }
   if (f) BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
   if (g) BPCHK(up(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, g, 8));
@@ -1640,7 +1660,7 @@ bp_status bp_apply_elastic(bp_solver* s, int32_t level, const double* g, const d
   if ((fine && r) || (!fine && Ft)) return fail(BP_ERR_ARG, "r applies to coarse levels, Ft to the finest");
   const LevelLay& v = P.lo.lv[level];
   LevelD& D = P.d.lv[level];
-  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
   BPCHK(up(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
   if (!fine) BPCHK(up(st, v.dbl, D.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
   if (fine) BPCHK(up(st, P.lo.fdbl, P.d.Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));
@@ -1658,7 +1678,7 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
   if ((fine && r) || (!fine && Ft)) return fail(BP_ERR_ARG, "r applies to coarse levels, Ft to the finest");
   const LevelLay& v = P.lo.lv[level];
   LevelD& D = P.d.lv[level];
-  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.fdbl ? 8 : 4)), st));
+  if (fine && P.lo.shift) HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
   BPCHK(up(st, v.dbl, D.gA, v.nx, v.ny, v.pitch, v.plane, g, 8));
   if (!fine) BPCHK(up(st, v.dbl, D.r, v.nx, v.ny, v.pitch, v.plane, r, 8));
   if (fine) BPCHK(up(st, P.lo.fdbl, P.d.Ft, v.nx, v.ny, v.pitch, v.plane, Ft, 2));

@@ -49,6 +49,7 @@ struct ProbD {
   void* Ft;                   // explicit force (2 planes)
   void* eref;                 // displacement reference (shifted storage) or null
   void* eref2;                // its second buffer, written by a re-basing sweep
+  int ref64;                  // references (eref, eref2, pref) in FP64, else FP32
   void* pref;                 // pressure reference (shifted storage) or null
   double* eta;                // extraction output (2 dense planes)
   double* sig;                // extraction output (3 dense planes)
@@ -170,9 +171,15 @@ inline int sweepn_tile_y(int A, bool dbl, bool shift, bool alt) {
   return rr - 4 * A;
 }
 // ALT: the alternative region of the applications per launch (not for four
-// applications without the restriction)
+// applications without the restriction); ref64: shifted FP32 storage where
+// some problem of the launch keeps FP64 references (selects the kernel variant
+// that reads either precision, per problem)
 template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT = false>
-hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s);
+hipError_t launch_tsweep2(const SweepL& a, int ntiles, bool ref64, hipStream_t s);
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT = false>
+inline hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
+  return launch_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT>(a, ntiles, false, s);
+}
 template <typename T, bool SHIFT>
 hipError_t launch_tflow(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>

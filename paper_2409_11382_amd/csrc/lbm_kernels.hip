@@ -16,6 +16,8 @@
 // The flow step uses the same tiling with a one-row halo.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_engine.h"
 
 namespace biot {
@@ -56,7 +58,10 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
   constexpr int NK = RR / 4;     // rows owned by each wave (two pairs)
   __shared__ T sD[RR][kWave];
   __shared__ T sS[8][CR][kWave];
-  __shared__ T sE[SHIFT ? 2 : 1][SHIFT ? CR : 1][kWave];
+  // shifted storage: the displacement reference, two FP64 planes or (in the
+  // same bytes) two FP32 planes
+  __shared__ std::conditional_t<SHIFT, double, T> sEd[SHIFT ? 2 : 1][SHIFT ? CR : 1][kWave];
+  float (*sEf)[SHIFT ? CR : 1][kWave] = reinterpret_cast<float (*)[SHIFT ? CR : 1][kWave]>(sEd);
   __shared__ double sRed[8];
 
   const int2 te = a.tiles[blockIdx.x];
@@ -83,7 +88,8 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
   const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
   const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
   Tc* rc = (MODE == kRestrict && l > 1) ? (Tc*)P.lv[l - 1].r : nullptr;
-  const T* eref = SHIFT ? (const T*)(a.eref_in ? P.eref2 : P.eref) : nullptr;
+  const void* eref = SHIFT ? (a.eref_in ? P.eref2 : P.eref) : nullptr;
+  const bool r64 = P.ref64 != 0;  // reference precision (uniform)
   ElConst<T> k;
   k.om_s = T(P.om_s);
   k.om_d = T(P.om_d);
@@ -116,8 +122,13 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
     Fx[kk] = (ok && crow && Ft) ? Ft[idx] : T(0);
     Fy[kk] = (ok && crow && Ft) ? Ft[plane + idx] : T(0);
     if (SHIFT && crow) {
-      sE[0][j - 1][lane] = ok ? eref[idx] : T(0);
-      sE[1][j - 1][lane] = ok ? eref[plane + idx] : T(0);
+      if (r64) {
+        sEd[0][j - 1][lane] = ok ? ((const double*)eref)[idx] : 0.0;
+        sEd[1][j - 1][lane] = ok ? ((const double*)eref)[plane + idx] : 0.0;
+      } else {
+        sEf[0][j - 1][lane] = ok ? ((const float*)eref)[idx] : 0.f;
+        sEf[1][j - 1][lane] = ok ? ((const float*)eref)[plane + idx] : 0.f;
+      }
     }
   }
   __syncthreads();
@@ -162,14 +173,35 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
     T gi[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
-    T ex = T(0), ey = T(0);
-    if (SHIFT) {
-      ex = sE[0][c][lc];
-      ey = sE[1][c][lc];
+    double ex = 0.0, ey = 0.0;
+    if (SHIFT && r64) {  // reference differences in FP64, rounded once
+      ex = sEd[0][c][lc];
+      ey = sEd[1][c][lc];
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        gi[q] += el_geq<T>(q, sE[0][c - cy8(q)][lc - cx8(q)] - ex, sE[1][c - cy8(q)][lc - cx8(q)] - ey);
+        gi[q] += T(el_geq<double>(q, sEd[0][c - cy8(q)][lc - cx8(q)] - ex, sEd[1][c - cy8(q)][lc - cx8(q)] - ey));
+    } else if (SHIFT) {
+      const float exf = sEf[0][c][lc], eyf = sEf[1][c][lc];
+      ex = exf;
+      ey = eyf;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        gi[q] += T(el_geq<float>(q, sEf[0][c - cy8(q)][lc - cx8(q)] - exf, sEf[1][c - cy8(q)][lc - cx8(q)] - eyf));
     }
+    // wall rules against the reference: FP64 with FP64 references, else in
+    // the population precision. Mirror rules take the source's reference
+    // (population qm) minus this cell's (population qq); bounce-back rules
+    // twice this cell's.
+    auto mirror = [&](int qm, int qq, int cc, int ll) -> T {
+      if constexpr (SHIFT) {
+        if (r64) return T(el_geq<double>(qm, sEd[0][cc][ll], sEd[1][cc][ll]) - el_geq<double>(qq, ex, ey));
+        return el_geq<T>(qm, T(sEf[0][cc][ll]), T(sEf[1][cc][ll])) - el_geq<T>(qq, T(ex), T(ey));
+      }
+      return T(0);
+    };
+    auto twice_own = [&](int qq) -> T {
+      return r64 ? T(2.0 * el_geq<double>(qq, ex, ey)) : T(2) * el_geq<T>(qq, T(ex), T(ey));
+    };
     const bool wb = valid && y == 0 && !pery;
     const bool wt = valid && y == ny - 1 && !pery;
     if (wl || wr || wb || wt) {
@@ -187,7 +219,7 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
           if (elx == kElSymmetry && ely == kElSymmetry) {
             // corner between two mirrors: diagonal bounce-back
             v = sS[opp8(q)][c][lc];
-            if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+            if (SHIFT) v -= twice_own(q);
           } else {
             usex = ely == kElSymmetry;
             half = true;
@@ -196,14 +228,14 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
           usex = true;
           if (elx == kElSymmetry) {  // mirror image: own column, row y - cy
             v = sS[mx8(q)][c - cy][lc];
-            if (SHIFT) v += el_geq<T>(mx8(q), sE[0][c - cy][lc], sE[1][c - cy][lc]) - el_geq<T>(q, ex, ey);
+            if (SHIFT) v += mirror(mx8(q), q, c - cy, lc);
           } else {
             half = true;
           }
         } else {
           if (ely == kElSymmetry) {  // mirror image: column x - cx, own row
             v = sS[my8(q)][c][lc - cx];
-            if (SHIFT) v += el_geq<T>(my8(q), sE[0][c][lc - cx], sE[1][c][lc - cx]) - el_geq<T>(q, ex, ey);
+            if (SHIFT) v += mirror(my8(q), q, c, lc - cx);
           } else {
             half = true;
           }
@@ -214,13 +246,15 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
                                           : (cy > 0 ? P.elbc[kBottom] : P.elbc[kTop]))
                                   : nullptr;
           const int bidx = usex ? y : x;
-          const T add = bc ? T(bc[8 * bidx + q]) : T(0);
+          const double add = bc ? bc[8 * bidx + q] : 0.0;
           const T o = sS[opp8(q)][c][lc];
           if (type == kElDirichlet) {
-            v = o + add;
-            if (SHIFT) v -= T(2) * el_geq<T>(q, ex, ey);
+            if (SHIFT && r64)  // the wall term and the reference's share in FP64, rounded once
+              v = o + T(add - 2.0 * el_geq<double>(q, ex, ey));
+            else
+              v = o + T(add) - (SHIFT ? twice_own(q) : T(0));
           } else {
-            v = -o + add;  // traction
+            v = -o + T(add);  // traction
           }
         }
         gi[q] = v;
@@ -231,7 +265,7 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
       for (int q = 0; q < 8; ++q) {
         const double rho = double(G[kk][q]) - double(gi[q]);
         double gf = double(G[kk][q]);
-        if (SHIFT) gf += double(el_geq<T>(q, ex, ey));
+        if (SHIFT) gf += el_geq<double>(q, ex, ey);
         acc_r += rho * rho;
         acc_g += gf * gf;
       }
@@ -299,7 +333,10 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 // the first ghost row/column of D must be restored by reflection (the loaded
 // ghosts were reflected copies; after an application they hold unused
 // values): columns by a lane permutation, rows through LDS.
-template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT>
+// R64: shifted storage whose references may be FP64 (FP64 populations, or a
+// problem above the size where FP32 references lose accuracy); without it the
+// reference arithmetic is FP32 only.
+template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT, bool R64>
 __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())) void k_tsweep2(SweepL a) {
   if (a.skip && *a.skip) return;  // uniform over the grid
   constexpr int A = APPS + (RES ? 1 : 0);
@@ -314,9 +351,10 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
   constexpr int TXO = RX - 2 * H;
   __shared__ T sD[RR][RX];
   __shared__ T sS[8][RR - 2][RX];
-  // shifted storage: reference ex, ey and the sums ex + ey, ey - ex that the
-  // diagonal pulls' corrections need
-  __shared__ T sE[SHIFT ? 4 : 1][SHIFT ? RR : 1][RX];
+  // shifted storage: the displacement reference, two FP64 planes (ex, ey) or,
+  // in the same bytes, four FP32 planes (ex, ey, ex + ey, ey - ex)
+  __shared__ std::conditional_t<SHIFT, double, T> sEd[SHIFT ? 2 : 1][SHIFT ? RR : 1][RX];
+  float (*sEf)[SHIFT ? RR : 1][RX] = reinterpret_cast<float (*)[SHIFT ? RR : 1][RX]>(sEd);
   __shared__ double sRed[2 * NW];
 
   const int2 te = a.tiles[blockIdx.x];
@@ -346,7 +384,8 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
   const int cpitch = l > 1 ? P.lv[l - 1].pitch : 0;
   const int64_t cplane = l > 1 ? P.lv[l - 1].plane : 0;
   Tc* rc = (RES && l > 1) ? (Tc*)P.lv[l - 1].r : nullptr;
-  const T* eref = SHIFT ? (const T*)(a.eref_in ? P.eref2 : P.eref) : nullptr;
+  const void* eref = SHIFT ? (a.eref_in ? P.eref2 : P.eref) : nullptr;
+  const bool r64 = R64 && P.ref64 != 0;  // reference precision (uniform)
   ElConst<T> k;
   k.om_s = T(P.om_s);
   k.om_d = T(P.om_d);
@@ -358,7 +397,6 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
   T G[NK][8];
   T Rv[FINE ? 1 : NK][8];
   T Fx[FINE ? NK : 1], Fy[FINE ? NK : 1];
-  T Ex[SHIFT ? NK : 1], Ey[SHIFT ? NK : 1];  // own reference
 
   // ---- load the region (ghosts as reflected or periodic copies)
 #pragma unroll
@@ -384,12 +422,16 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
       for (int q = 0; q < 8; ++q) Rv[kk][q] = (ok && crow) ? rr[q * plane + idx] : T(0);
     }
     if (SHIFT) {
-      Ex[kk] = ok ? eref[idx] : T(0);
-      Ey[kk] = ok ? eref[plane + idx] : T(0);
-      sE[0][j][col] = Ex[kk];
-      sE[1][j][col] = Ey[kk];
-      sE[2][j][col] = Ex[kk] + Ey[kk];
-      sE[3][j][col] = Ey[kk] - Ex[kk];
+      if (r64) {
+        sEd[0][j][col] = ok ? ((const double*)eref)[idx] : 0.0;
+        sEd[1][j][col] = ok ? ((const double*)eref)[plane + idx] : 0.0;
+      } else {
+        const float ex = ok ? ((const float*)eref)[idx] : 0.f, ey = ok ? ((const float*)eref)[plane + idx] : 0.f;
+        sEf[0][j][col] = ex;
+        sEf[1][j][col] = ey;
+        sEf[2][j][col] = ex + ey;
+        sEf[3][j][col] = ey - ex;
+      }
     }
   }
 
@@ -479,25 +521,43 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
       T gi[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) gi[q] = sS[q][c - cy8(q)][lc - cx8(q)];
-      T ex = T(0), ey = T(0);
+      // own reference, read from LDS where a rule needs it (FP64 registers
+      // per row would cost occupancy)
+      auto own_x = [&]() { return r64 ? sEd[0][j][col] : double(sEf[0][j][col]); };
+      auto own_y = [&]() { return r64 ? sEd[1][j][col] : double(sEf[1][j][col]); };
       if (SHIFT) {
-        ex = Ex[kk];
-        ey = Ey[kk];
-        if (app == 0) {  // rows and columns pulled later are a subset
-          const T sp = ex + ey, sm = ey - ex;
-          const T third = T(1.0 / 3.0), twelfth = T(1.0 / 12.0);
-          Cr[kk][0] = third * (sE[0][j][lc - 1] - ex);
-          Cr[kk][1] = third * (sE[1][j - 1][lc] - ey);
-          Cr[kk][2] = -third * (sE[0][j][lc + 1] - ex);
-          Cr[kk][3] = -third * (sE[1][j + 1][lc] - ey);
-          Cr[kk][4] = twelfth * (sE[2][j - 1][lc - 1] - sp);
-          Cr[kk][5] = twelfth * (sE[3][j - 1][lc + 1] - sm);
-          Cr[kk][6] = -twelfth * (sE[2][j + 1][lc + 1] - sp);
-          Cr[kk][7] = -twelfth * (sE[3][j + 1][lc - 1] - sm);
+        if (app == 0 && r64) {  // rows and columns pulled later are a subset
+          // reference differences in FP64, rounded once
+          const double ex = sEd[0][j][col], ey = sEd[1][j][col];
+          const double sp = ex + ey, sm = ey - ex;
+          const double third = 1.0 / 3.0, twelfth = 1.0 / 12.0;
+          Cr[kk][0] = T(third * (sEd[0][j][lc - 1] - ex));
+          Cr[kk][1] = T(third * (sEd[1][j - 1][lc] - ey));
+          Cr[kk][2] = T(-third * (sEd[0][j][lc + 1] - ex));
+          Cr[kk][3] = T(-third * (sEd[1][j + 1][lc] - ey));
+          Cr[kk][4] = T(twelfth * ((sEd[0][j - 1][lc - 1] + sEd[1][j - 1][lc - 1]) - sp));
+          Cr[kk][5] = T(twelfth * ((sEd[1][j - 1][lc + 1] - sEd[0][j - 1][lc + 1]) - sm));
+          Cr[kk][6] = T(-twelfth * ((sEd[0][j + 1][lc + 1] + sEd[1][j + 1][lc + 1]) - sp));
+          Cr[kk][7] = T(-twelfth * ((sEd[1][j + 1][lc - 1] - sEd[0][j + 1][lc - 1]) - sm));
+        } else if (app == 0) {  // FP32 reference
+          const float exf = sEf[0][j][col], eyf = sEf[1][j][col];
+          const float sp = exf + eyf, sm = eyf - exf;
+          const float third = 1.0f / 3.0f, twelfth = 1.0f / 12.0f;
+          Cr[kk][0] = T(third * (sEf[0][j][lc - 1] - exf));
+          Cr[kk][1] = T(third * (sEf[1][j - 1][lc] - eyf));
+          Cr[kk][2] = T(-third * (sEf[0][j][lc + 1] - exf));
+          Cr[kk][3] = T(-third * (sEf[1][j + 1][lc] - eyf));
+          Cr[kk][4] = T(twelfth * (sEf[2][j - 1][lc - 1] - sp));
+          Cr[kk][5] = T(twelfth * (sEf[3][j - 1][lc + 1] - sm));
+          Cr[kk][6] = T(-twelfth * (sEf[2][j + 1][lc + 1] - sp));
+          Cr[kk][7] = T(-twelfth * (sEf[3][j + 1][lc - 1] - sm));
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) gi[q] += sc * Cr[kk][q];
       }
+      // the reference of a neighbour (wall rules), in FP64
+      auto rx = [&](int jj, int ll) { return r64 ? sEd[0][jj][ll] : double(sEf[0][jj][ll]); };
+      auto ry = [&](int jj, int ll) { return r64 ? sEd[1][jj][ll] : double(sEf[1][jj][ll]); };
       bool wl = false, wr = false, wb = false, wt = false;
       int gy = 0;
       if (bnd) {
@@ -510,6 +570,19 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
         wt = real && !pery && y == ny - 1;
       }
       if (bnd && (wl || wr || wb || wt)) {
+        // wall terms against the reference: FP64 with FP64 references, else in
+        // the population precision
+        const double ex = SHIFT ? own_x() : 0.0, ey = SHIFT ? own_y() : 0.0;
+        const T ext = T(ex), eyt = T(ey);
+        // mirror rules: the source's reference (population qm) minus this
+        // cell's (population qq); bounce-back rules: twice this cell's
+        auto mirror = [&](int qm, int qq, int jj, int ll) -> T {
+          if (r64) return T(el_geq<double>(qm, rx(jj, ll), ry(jj, ll)) - el_geq<double>(qq, ex, ey));
+          return el_geq<T>(qm, T(rx(jj, ll)), T(ry(jj, ll))) - el_geq<T>(qq, ext, eyt);
+        };
+        auto twice_own = [&](int qq) -> T {
+          return r64 ? T(2.0 * el_geq<double>(qq, ex, ey)) : T(2) * el_geq<T>(qq, ext, eyt);
+        };
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int cx = cx8(q), cy = cy8(q);
@@ -523,7 +596,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
           if (ox && oy) {
             if (elx == kElSymmetry && ely == kElSymmetry) {
               v = sS[opp8(q)][c][lc];
-              if (SHIFT) v -= sc * (T(2) * el_geq<T>(q, ex, ey));
+              if (SHIFT) v -= sc * twice_own(q);
             } else {
               usex = ely == kElSymmetry;
               half = true;
@@ -532,14 +605,14 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
             usex = true;
             if (elx == kElSymmetry) {
               v = sS[mx8(q)][c - cy][lc];
-              if (SHIFT) v += sc * (el_geq<T>(mx8(q), sE[0][j - cy][lc], sE[1][j - cy][lc]) - el_geq<T>(q, ex, ey));
+              if (SHIFT) v += sc * mirror(mx8(q), q, j - cy, lc);
             } else {
               half = true;
             }
           } else {
             if (ely == kElSymmetry) {
               v = sS[my8(q)][c][lc - cx];
-              if (SHIFT) v += sc * (el_geq<T>(my8(q), sE[0][j][lc - cx], sE[1][j][lc - cx]) - el_geq<T>(q, ex, ey));
+              if (SHIFT) v += sc * mirror(my8(q), q, j, lc - cx);
             } else {
               half = true;
             }
@@ -550,13 +623,18 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
                                             : (cy > 0 ? P.elbc[kBottom] : P.elbc[kTop]))
                                     : nullptr;
             const int bidx = usex ? gy : gx;
-            const T add = bc ? sc * T(bc[8 * bidx + q]) : T(0);
             const T o = sS[opp8(q)][c][lc];
-            if (type == kElDirichlet) {
-              v = o + add;
-              if (SHIFT) v -= sc * (T(2) * el_geq<T>(q, ex, ey));
+            if (SHIFT && r64 && type == kElDirichlet) {
+              // the wall term and the reference's share in FP64, rounded once
+              v = o + sc * T((bc ? bc[8 * bidx + q] : 0.0) - 2.0 * el_geq<double>(q, ex, ey));
             } else {
-              v = -o + add;
+              const T add = bc ? sc * T(bc[8 * bidx + q]) : T(0);
+              if (type == kElDirichlet) {
+                v = o + add;
+                if (SHIFT) v -= sc * twice_own(q);
+              } else {
+                v = -o + add;
+              }
             }
           }
           gi[q] = v;
@@ -583,11 +661,12 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
         }
       } else if (!RES && app == A - 1) {
         if (a.partials && out) {
+          const double ex = SHIFT ? own_x() : 0.0, ey = SHIFT ? own_y() : 0.0;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const double rho = double(G[kk][q]) - double(gi[q]) * inv_gam;
             double gf = double(G[kk][q]);
-            if (SHIFT) gf += double(el_geq<T>(q, ex, ey));
+            if (SHIFT) gf += el_geq<double>(q, ex, ey);
             acc_r += rho * rho;
             acc_g += gf * gf;
           }
@@ -604,9 +683,15 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
             const T m01 = (gn[1] - gn[3]) + (gn[4] + gn[5]) - (gn[6] + gn[7]);
 #pragma unroll
             for (int q = 0; q < 8; ++q) gn[q] -= el_geq<T>(q, m10, m01);
-            T* eo = (T*)(a.eref_in ? P.eref : P.eref2);
-            eo[oidx] = ex + m10;
-            eo[plane + oidx] = ey + m01;
+            void* eo = a.eref_in ? P.eref : P.eref2;
+            const double ex = own_x(), ey = own_y();
+            if (r64) {
+              ((double*)eo)[oidx] = ex + double(m10);
+              ((double*)eo)[plane + oidx] = ey + double(m01);
+            } else {
+              ((float*)eo)[oidx] = float(ex) + float(m10);
+              ((float*)eo)[plane + oidx] = float(ey) + float(m01);
+            }
           }
 #pragma unroll
           for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = gn[q];
@@ -663,10 +748,18 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
 }
 
 template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT>
-hipError_t launch_tsweep2(const SweepL& a, int ntiles, hipStream_t s) {
+hipError_t launch_tsweep2(const SweepL& a, int ntiles, bool ref64, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT>), dim3(ntiles),
-                     dim3(kWave * sweepn_waves<T, SHIFT, APPS + (RES ? 1 : 0), ALT>()), 0, s, a);
+  const dim3 block(kWave * sweepn_waves<T, SHIFT, APPS + (RES ? 1 : 0), ALT>());
+  constexpr bool dbl = std::is_same<T, double>::value;
+  if constexpr (SHIFT && !dbl) {
+    if (ref64)
+      hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT, true>), dim3(ntiles), block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT, false>), dim3(ntiles), block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_tsweep2<T, Tc, FINE, SHIFT, APPS, RES, ALT, SHIFT && dbl>), dim3(ntiles), block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -681,7 +774,8 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
   constexpr int RR = TY + 2;                 // one halo row each side
   constexpr int NK = (RR + 3) / 4;
   __shared__ T sF[9][RR][kWave];
-  __shared__ T sP[SHIFT ? RR : 1][kWave];
+  __shared__ double sPd[SHIFT ? RR : 1][kWave];  // pressure reference, FP64 or FP32 (same bytes)
+  float (*sPf)[kWave] = reinterpret_cast<float (*)[kWave]>(sPd);
 
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
@@ -704,7 +798,8 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
   const bool col_ok = x >= -1 && x < nx + 1;
   const int gx = col_ok ? ghost_map(x, nx, perx) : 0;
   const bool out_lane = lane >= kHalo && lane < kWave - kHalo && x < nx;
-  T* pref = SHIFT ? (T*)P.pref : nullptr;
+  void* pref = SHIFT ? P.pref : nullptr;
+  const bool r64 = P.ref64 != 0;
 
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk) {
@@ -713,7 +808,8 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
     const int y = y0 - 1 + j;
     const bool ok = col_ok && y >= -1 && y < ny + 1;
     T f[9];
-    T s = T(0), om = T(P.omf_u), pr = T(0);
+    T s = T(0), om = T(P.omf_u);
+    double pr = 0.0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) f[i] = T(0);
     if (ok) {
@@ -730,13 +826,13 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
       if (P.src) sv += P.src[idx];
       s = T(sv);
       if (P.omf) om = T(P.omf[idx]);
-      if (SHIFT) pr = pref[idx];
+      if (SHIFT) pr = r64 ? ((const double*)pref)[idx] : double(((const float*)pref)[idx]);
       if (out_lane && j >= 1 && j <= TY && y < ny) {
         Dn[idx] = dn;
         T sum = T(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sum += f[i];
-        P.pout[idx] = double(sum) + 0.5 * sv + double(pr);
+        P.pout[idx] = double(sum) + 0.5 * sv + pr;
       }
     }
     T p = T(0);
@@ -749,7 +845,12 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
       const T wi = T(w9(i));
       sF[i][j][lane] = f[i] - om * (f[i] - wi * p) + wi * so;
     }
-    if (SHIFT) sP[j][lane] = pr;
+    if (SHIFT) {
+      if (r64)
+        sPd[j][lane] = pr;
+      else
+        sPf[j][lane] = float(pr);
+    }
   }
   __syncthreads();
 
@@ -763,12 +864,18 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
     T fo[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fo[i] = sF[i][j - cy9(i)][lane - cx9(i)];
-    T p0 = T(0);
-    if (SHIFT) {
-      p0 = sP[j][lane];
+    double p0 = 0.0;
+    if (SHIFT && r64) {  // reference differences in FP64, rounded once
+      p0 = sPd[j][lane];
 #pragma unroll
-      for (int i = 1; i < 9; ++i) fo[i] += T(w9(i)) * (sP[j - cy9(i)][lane - cx9(i)] - p0);
+      for (int i = 1; i < 9; ++i) fo[i] += T(w9(i) * (sPd[j - cy9(i)][lane - cx9(i)] - p0));
+    } else if (SHIFT) {
+      const float p0f = sPf[j][lane];
+      p0 = p0f;
+#pragma unroll
+      for (int i = 1; i < 9; ++i) fo[i] += T(float(w9(i)) * (sPf[j - cy9(i)][lane - cx9(i)] - p0f));
     }
+    auto pn = [&](int jj, int ll) { return r64 ? sPd[jj][ll] : double(sPf[jj][ll]); };
     const int tL = P.ftype[kLeft][y], tR = P.ftype[kRight][y];
     const int tB = P.ftype[kBottom][x], tT = P.ftype[kTop][x];
     const bool wl = x == 0 && tL != kFlPeriodic;
@@ -797,14 +904,14 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
           usex = true;
           if (tx_ == kFlSymmetry) {
             v = sF[mx9(i)][j - cy][lane];
-            if (SHIFT) v += T(w9(i)) * (sP[j - cy][lane] - p0);
+            if (SHIFT) v += T(w9(i) * (pn(j - cy, lane) - p0));
           } else {
             half = true;
           }
         } else {
           if (ty_ == kFlSymmetry) {
             v = sF[my9(i)][j][lane - cx];
-            if (SHIFT) v += T(w9(i)) * (sP[j][lane - cx] - p0);
+            if (SHIFT) v += T(w9(i) * (pn(j, lane - cx) - p0));
           } else {
             half = true;
           }
@@ -818,8 +925,8 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
             const double* bc = usex ? (cx > 0 ? P.flbc[kLeft] : P.flbc[kRight])
                                     : (cy > 0 ? P.flbc[kBottom] : P.flbc[kTop]);
             const int bidx = usex ? y : x;
-            v = -o + (bc ? T(bc[9 * bidx + i]) : T(0));
-            if (SHIFT) v -= T(2.0 * w9(i)) * p0;
+            const double add = bc ? bc[9 * bidx + i] : 0.0;
+            v = -o + T(SHIFT ? add - 2.0 * w9(i) * p0 : add);  // one rounding
           }
         }
         fo[i] = v;
@@ -871,7 +978,8 @@ __device__ __forceinline__ void force_stage(const ProbD& P, const LevelD& V, int
   const double* D1 = P.D[(n + 2) % 3];
   const double* D2 = P.D[(n + 1) % 3];
   const T* f = (const T*)P.f[n & 1];
-  const T* pref = (const T*)P.pref;
+  const void* pref = P.pref;
+  const bool r64 = P.ref64 != 0;
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
   for (int r = threadIdx.x; r < kFRX * kFRY; r += blockDim.x) {
     const int rx = r % kFRX, ry = r / kFRX;
@@ -885,7 +993,7 @@ __device__ __forceinline__ void force_stage(const ProbD& P, const LevelD& V, int
     sst[ry][rx] = v;
     if (CENTRAL) {
       // shifted storage holds f - w p_ref, whose sum lacks p_ref
-      double sum = pref ? double(pref[k]) : 0.0;
+      double sum = pref ? (r64 ? ((const double*)pref)[k] : double(((const float*)pref)[k])) : 0.0;
 #pragma unroll
       for (int i = 0; i < 9; ++i) sum += double(f[i * V.plane + k]);
       sp[ry][rx] = sum;
@@ -1006,11 +1114,15 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 #pragma unroll
   for (int q = 0; q < 8; ++q) gA[q * V.plane + idx] = T(g[q]);
   for (int k = 0; k < 3; ++k) P.D[k][idx] = 0.0;
-  if (P.eref) {
-    ((T*)P.eref)[idx] = T(0);
-    ((T*)P.eref)[V.plane + idx] = T(0);
+  if (P.eref && P.ref64) {
+    ((double*)P.eref)[idx] = 0.0;
+    ((double*)P.eref)[V.plane + idx] = 0.0;
+    ((double*)P.pref)[idx] = 0.0;
+  } else if (P.eref) {
+    ((float*)P.eref)[idx] = 0.f;
+    ((float*)P.eref)[V.plane + idx] = 0.f;
+    ((float*)P.pref)[idx] = 0.f;
   }
-  if (P.pref) ((T*)P.pref)[idx] = T(0);
   P.pout[idx] = 0.0;
 }
 
@@ -1039,9 +1151,15 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   const T m01 = (u[1] - u[3]) + (u[4] + u[5]) - (u[6] + u[7]);
 #pragma unroll
   for (int q = 0; q < 8; ++q) g[q * V.plane + idx] = u[q] - el_geq<T>(q, m10, m01);
-  T* eref = (T*)P.eref;
-  eref[idx] += m10;
-  eref[V.plane + idx] += m01;
+  if (P.ref64) {
+    double* eref = (double*)P.eref;
+    eref[idx] += double(m10);
+    eref[V.plane + idx] += double(m01);
+  } else {
+    float* eref = (float*)P.eref;
+    eref[idx] += float(m10);
+    eref[V.plane + idx] += float(m01);
+  }
   if (!FLOW) return;
   T* f = (T*)P.f[(*P.phase) & 1];
   T fv[9];
@@ -1061,7 +1179,10 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
       jy += double(v) * cy9(i);
     }
   }
-  ((T*)P.pref)[idx] += p;
+  if (P.ref64)
+    ((double*)P.pref)[idx] += double(p);
+  else
+    ((float*)P.pref)[idx] += float(p);
   // the step's explicit force from the re-based populations, as k_force
   // (first-moment gradient only: it reads no neighbour's populations)
   if (FORCE) {
@@ -1106,8 +1227,8 @@ __global__ __launch_bounds__(256) void k_extract(CellL a) {
   const double ms = ((u[0] + u[2]) + (u[1] + u[3])) + 2.0 * ((u[4] + u[5]) + (u[6] + u[7]));
   const double md = (u[0] + u[2]) - (u[1] + u[3]);
   if (SHIFT) {
-    m10 += double(((const T*)P.eref)[idx]);
-    m01 += double(((const T*)P.eref)[V.plane + idx]);
+    m10 += P.ref64 ? ((const double*)P.eref)[idx] : double(((const float*)P.eref)[idx]);
+    m01 += P.ref64 ? ((const double*)P.eref)[V.plane + idx] : double(((const float*)P.eref)[V.plane + idx]);
   }
   const int64_t o = (int64_t)c.y * V.nx + c.x, N = (int64_t)V.nx * V.ny;
   P.eta[o] = m10 + 0.5 * Fx;
@@ -1649,42 +1770,42 @@ BIOT_SWEEP(float, double)
 BIOT_SWEEP(double, double)
 #undef BIOT_SWEEP
 #define BIOT_SWEEPN_ALT(T, Tc, ALT)                                                                    \
-  template hipError_t launch_tsweep2<T, Tc, true, true, 2, false, ALT>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 2, false, ALT>(const SweepL&, int, hipStream_t); \
-  template hipError_t launch_tsweep2<T, Tc, true, true, 2, true, ALT>(const SweepL&, int, hipStream_t);   \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 2, true, ALT>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 2, false, ALT>(const SweepL&, int, hipStream_t); \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 2, true, ALT>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true, ALT>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true, ALT>(const SweepL&, int, hipStream_t);
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, false, ALT>(const SweepL&, int, bool, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, false, ALT>(const SweepL&, int, bool, hipStream_t); \
+  template hipError_t launch_tsweep2<T, Tc, true, true, 2, true, ALT>(const SweepL&, int, bool, hipStream_t);   \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 2, true, ALT>(const SweepL&, int, bool, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, false, ALT>(const SweepL&, int, bool, hipStream_t); \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 2, true, ALT>(const SweepL&, int, bool, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, true, ALT>(const SweepL&, int, bool, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, true, ALT>(const SweepL&, int, bool, hipStream_t);
 #define BIOT_SWEEPN(T, Tc)                                                                            \
   BIOT_SWEEPN_ALT(T, Tc, false)                                                                       \
   BIOT_SWEEPN_ALT(T, Tc, true)                                                                        \
-  template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, hipStream_t);  \
-  template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, hipStream_t);
+  template hipError_t launch_tsweep2<T, Tc, false, false, 4, false>(const SweepL&, int, bool, hipStream_t);  \
+  template hipError_t launch_tsweep2<T, Tc, true, false, 4, false>(const SweepL&, int, bool, hipStream_t);
 BIOT_SWEEPN(float, float)
 BIOT_SWEEPN(float, double)
 BIOT_SWEEPN(double, double)
 #undef BIOT_SWEEPN
 #undef BIOT_SWEEPN_ALT
-template hipError_t launch_tsweep2<float, float, true, true, 4, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, true, true, 4, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, true, 4, false>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, true, 4, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, float, true, true, 4, true, true>(const SweepL&, int, hipStream_t);
-template hipError_t launch_tsweep2<float, double, true, true, 4, true, true>(const SweepL&, int, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 4, false>(const SweepL&, int, bool, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 4, true>(const SweepL&, int, bool, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, false>(const SweepL&, int, bool, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, true>(const SweepL&, int, bool, hipStream_t);
+template hipError_t launch_tsweep2<float, float, true, true, 4, true, true>(const SweepL&, int, bool, hipStream_t);
+template hipError_t launch_tsweep2<float, double, true, true, 4, true, true>(const SweepL&, int, bool, hipStream_t);
 // FP64 shifted storage has no LDS room for four applications; the schedule
 // never asks for them (these stubs keep the dispatch table complete)
 template <>
-hipError_t launch_tsweep2<double, double, true, true, 4, false>(const SweepL&, int, hipStream_t) {
+hipError_t launch_tsweep2<double, double, true, true, 4, false>(const SweepL&, int, bool, hipStream_t) {
   return hipErrorInvalidConfiguration;
 }
 template <>
-hipError_t launch_tsweep2<double, double, true, true, 4, true>(const SweepL&, int, hipStream_t) {
+hipError_t launch_tsweep2<double, double, true, true, 4, true>(const SweepL&, int, bool, hipStream_t) {
   return hipErrorInvalidConfiguration;
 }
 template <>
-hipError_t launch_tsweep2<double, double, true, true, 4, true, true>(const SweepL&, int, hipStream_t) {
+hipError_t launch_tsweep2<double, double, true, true, 4, true, true>(const SweepL&, int, bool, hipStream_t) {
   return hipErrorInvalidConfiguration;
 }
 template hipError_t launch_tflow<float, false>(const CellL&, int, hipStream_t);

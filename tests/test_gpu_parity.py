@@ -280,6 +280,50 @@ def test_shifted_fp64_equals_plain_fp64(lbm):
     assert rel(B["eta"], A["eta"]) < 1e-13 and rel(B["p"], A["p"]) < 1e-12
 
 
+def test_fp32_shifted_with_fp64_references(lbm, monkeypatch):
+    """FP32 shifted storage with its references in FP64 (the library's choice
+    on grids above 4096^2 cells; forced here) on mixed boundaries and with
+    the re-bases between cycles, against the oracle."""
+    monkeypatch.setenv("BIOT_REF64", "1")
+    p = mixed_walls(124, 68, seed=7).replace(ne_fixed=3, K=4)
+    s = lbm.Solver(p, "fp32_shifted")
+    s.step(6)
+    A = s.fields()
+    s.close()
+    o = Oracle(p, threads=oracle_threads())
+    o.step(6)
+    B = o.fields()
+    e = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+    _say("fp32 shifted, FP64 references", e)
+    assert max(e) < 1e-5
+
+
+def test_batch_mixed_reference_precisions(lbm, monkeypatch):
+    """One batch whose FP32 shifted problems keep their references in
+    different precisions (FP64 above a cell count, lowered here to 96^2): its
+    launches read either precision per problem.  Every problem matches the
+    oracle and, to rounding, the same problem run alone."""
+    monkeypatch.setenv("BIOT_REF64_CELLS", str(96 * 96))
+    probs = [mixed_walls(124, 68, seed=7).replace(ne_fixed=3, K=4),   # FP32 references
+             mixed_walls(128, 96, seed=3).replace(ne_fixed=3, K=4),   # FP64 references
+             P.loaded_strip(n=64, alpha=1.0, ne_fixed=3)]             # FP32 references
+    b = lbm.Batch(probs, "fp32_shifted")
+    b.step(6)
+    for i, p in enumerate(probs):
+        B = b.fields(i)
+        s = lbm.Solver(p, "fp32_shifted")
+        s.step(6)
+        A = s.fields()
+        s.close()
+        o = Oracle(p, threads=oracle_threads())
+        o.step(6)
+        C = o.fields()
+        d = (rel(B["eta"], A["eta"]), rel(B["p"], A["p"]))
+        e = (rel(B["eta"], C["eta"]), rel(B["p"], C["p"]), rel(B["sigma"], C["sigma"]))
+        _say("mixed references", i, p.nx, p.ny, d, e)
+        assert max(d) < 1e-6 and max(e) < 1e-5, (i, d, e)
+
+
 @pytest.mark.parametrize("K,ne", [(3, 4), (2, 2), (4, 5)])
 def test_shifted_rebase_schedules(lbm, K, ne):
     """Shifted storage re-bases between V-cycles inside the cycle's last
