@@ -144,7 +144,11 @@ bp_status bp_get_fields(bp_solver *s, double *eta, double *p, double *sigma, int
 /* Checkpoint access in FP64 component planes: f (9 x N, D2Q9 order of Table 1),
  * g (8 x N, D2Q8 order 10,01,-10,0-1,11,-11,-1-1,1-1, full populations),
  * D1 = D^{n-1}, D2 = D^{n-2} (lattice divergences, N each).  bp_set_state also
- * sets the step counter. */
+ * sets the step counter; a NULL array leaves that part of the state as it is.
+ * In shifted storage bp_set_state splits f and g in FP64 into the references
+ * the step-start re-base would take (the displacement moments of g, the sum
+ * of f) and the offsets from them, so a restored state carries the same
+ * rounding as one the solver reached itself. */
 bp_status bp_get_state(bp_solver *s, double *f, double *g, double *D1, double *D2, int32_t *step);
 bp_status bp_set_state(bp_solver *s, const double *f, const double *g, const double *D1,
                        const double *D2, int32_t step);

@@ -1631,12 +1631,43 @@ bp_status bp_set_state(bp_solver* s, const double* f, const double* g, const dou
   const int n = step;
   int ph[2] = {n, 0};  // phase, flags
   HIPCHK(hipMemcpyAsync(P.d.phase, ph, 2 * sizeof(int), hipMemcpyHostToDevice, st));
-  if (P.lo.shift) {  // references to zero: stored offsets are the full populations
-    HIPCHK(launch_fill_zero(P.d.eref, align_up(2 * P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
-    HIPCHK(launch_fill_zero(P.d.pref, align_up(P.lo.plane * (P.lo.ref64 ? 8 : 4)), st));
+  if (P.lo.shift) {
+    // shifted storage: split the given populations as the step-start re-base
+    // does, in FP64 on the host: the references are the displacement moments
+    // of g and the zeroth moment of f (rounded to their storage precision),
+    // the stored offsets what remains.  The offsets are small, so storing
+    // them in the population precision keeps what FP32 full populations
+    // would round away.  A part not given keeps its offsets and reference.
+    const size_t N = (size_t)nx * ny;
+    auto to_ref = [&](double x) { return P.lo.ref64 ? x : double(float(x)); };
+    if (g) {
+      std::vector<double> er(2 * N), dg(8 * N);
+      for (size_t k = 0; k < N; ++k) {
+        const double* u = g + k;
+        const double m10 = (u[0] - u[2 * N]) + (u[4 * N] - u[5 * N]) + (u[7 * N] - u[6 * N]);
+        const double m01 = (u[N] - u[3 * N]) + (u[4 * N] + u[5 * N]) - (u[6 * N] + u[7 * N]);
+        er[k] = to_ref(m10);
+        er[N + k] = to_ref(m01);
+        for (int q = 0; q < 8; ++q) dg[q * N + k] = g[q * N + k] - geq_host(q, er[k], er[N + k]);
+      }
+      BPCHK(up(st, P.lo.ref64, P.d.eref, nx, ny, P.lo.pitch, P.lo.plane, er.data(), 2));
+      BPCHK(up(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, dg.data(), 8));
+    }
+    if (f) {
+      std::vector<double> pr(N), df(9 * N);
+      for (size_t k = 0; k < N; ++k) {
+        double sum = 0.0;
+        for (int i = 0; i < 9; ++i) sum += f[i * N + k];
+        pr[k] = to_ref(sum);
+        for (int i = 0; i < 9; ++i) df[i * N + k] = f[i * N + k] - W9[i] * pr[k];
+      }
+      BPCHK(up(st, P.lo.ref64, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
+      BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, df.data(), 9));
+    }
+  } else {
+    if (f) BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
+    if (g) BPCHK(up(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, g, 8));
   }
-  if (f) BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, f, 9));
-  if (g) BPCHK(up(st, v.dbl, P.d.lv[P.L].gA, nx, ny, v.pitch, v.plane, g, 8));
   if (D1) BPCHK(upload_planes<double>(st, P.d.D[(n + 2) % 3], nx, ny, P.lo.pitch, P.lo.plane, D1, 1));
   if (D2) BPCHK(upload_planes<double>(st, P.d.D[(n + 1) % 3], nx, ny, P.lo.pitch, P.lo.plane, D2, 1));
   HIPCHK(hipStreamSynchronize(st));

@@ -387,6 +387,42 @@ def test_checkpoint_resume_is_bitwise(lbm):
     assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
 
 
+@pytest.mark.parametrize("ref64", ["0", "1"])
+def test_checkpoint_shifted_storage(lbm, monkeypatch, ref64):
+    """FP32 shifted storage, FP32 and FP64 references.  A restored state is
+    split into references and offsets in FP64, so the round trip keeps what
+    FP32 full populations would round away: on a state with a displacement
+    and pressure of 1e3 (equilibria of ~300) it returns g and f within 1e-6
+    (FP32 full populations would lose ~2e-5).  A run resumed from a checkpoint
+    follows the uninterrupted run to rounding."""
+    monkeypatch.setenv("BIOT_REF64", ref64)
+    p = P.loaded_strip(n=64, alpha=0.8, ne_fixed=3)
+    a = lbm.Solver(p, "fp32_shifted")
+    a.step(6)
+    st = a.get_state()
+    a.step(4)
+    b = lbm.Solver(p, "fp32_shifted")
+    b.set_state(st["f"], st["g"], st["D1"], st["D2"], step=st["step"])
+    b.step(4)
+    A, B = a.fields(), b.fields()
+    d = (rel(B["eta"], A["eta"]), rel(B["p"], A["p"]))
+    # a large rigid displacement and pressure offset on top of the state
+    E, P0 = 1e3, 1e3
+    w8 = np.array([1 / 3, 1 / 3, 1 / 3, 1 / 3, 1 / 12, 1 / 12, 1 / 12, 1 / 12])
+    c8 = np.array([[1, 0], [0, 1], [-1, 0], [0, -1], [1, 1], [-1, 1], [-1, -1], [1, -1]])
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    g = st["g"] + (w8 * (c8[:, 0] * E + c8[:, 1] * E))[:, None, None]
+    f = st["f"] + (w9 * P0)[:, None, None]
+    b.set_state(f, g, st["D1"], st["D2"], step=st["step"])
+    rt = b.get_state()
+    eg, ef = np.abs(rt["g"] - g).max(), np.abs(rt["f"] - f).max()
+    _say("checkpoint shifted ref64", ref64, d, "round trip", eg, ef)
+    assert max(d) < 1e-6, d
+    assert eg < 1e-6 and ef < 1e-6, (eg, ef)
+    a.close()
+    b.close()
+
+
 def test_full_size_loaded_strip_512(lbm):
     """The benchmarked workload (loaded strip 512 x 512, alpha = 1, MG(3,4)) at
     its real size for a few steps, FP64 against the oracle, plus the FP32
