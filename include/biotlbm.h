@@ -156,7 +156,12 @@ bp_status bp_set_state(bp_solver *s, const double *f, const double *g, const dou
 /* Single operations on host FP64 planes (lattice units), for inspection:
  * out = S(g) = ELASTIC_STEP(g - r, Ft + F_*(g)) on level l (l = levels is the
  * finest, Algorithm 4 line with g**), one ELASTIC_MULTIGRID cycle on level l
- * (g in/out), and the explicit force of the current state (2 x N). */
+ * (g in/out), and the explicit force of the current state (2 x N).
+ * bp_apply_elastic and bp_mg_cycle work in the solver's own buffers: they
+ * replace its elastic populations, force and (shifted storage) displacement
+ * reference, so a solver that is to step on afterwards needs bp_set_state
+ * (or bp_set_loads with reinit) first.  bp_explicit_force leaves the state
+ * alone. */
 bp_status bp_apply_elastic(bp_solver *s, int32_t level, const double *g, const double *r,
                            const double *Ft, double *out);
 bp_status bp_mg_cycle(bp_solver *s, int32_t level, double *g, const double *r, const double *Ft);
