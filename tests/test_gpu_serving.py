@@ -94,6 +94,39 @@ def test_served_results_equal_alone(lbm, prec):
         assert rel(got[2]["eta"], o.fields()["eta"]) < 1e-10
 
 
+def test_served_mixed_reference_precisions(lbm, monkeypatch):
+    """FP32 shifted requests with FP64 references (above a cell count, lowered
+    here to 96^2) join and leave a running mix: the engine switches its sweep
+    kernels' reference variant as the mix changes (FP32 only, then both, then
+    FP32 only again), and every result matches the problem run alone."""
+    monkeypatch.setenv("BIOT_REF64_CELLS", str(96 * 96))
+    reqs = [(P.loaded_strip(n=64, alpha=0.7), 8),                         # FP32 references
+            (P.loaded_strip(n=128, alpha=1.0), 3),                        # FP64 references
+            (mixed_walls(124, 68, seed=9).replace(ne_fixed=3, K=4), 6)]   # FP32 references
+    srv = lbm.Server(1 << 30, prec="fp32_shifted", K=4, ne_fixed=3, max_slots=8)
+    tickets = {0: srv.submit(*reqs[0])}
+    srv.advance(2)
+    tickets[1] = srv.submit(*reqs[1])
+    srv.advance(1)
+    tickets[2] = srv.submit(*reqs[2])
+    got = {}
+    for _ in range(20):
+        srv.advance(1)
+        for i, t in list(tickets.items()):
+            if srv.poll(t)[0] == lbm.REQ_DONE:
+                got[i] = srv.result(t)
+                del tickets[i]
+        if not tickets:
+            break
+    srv.close()
+    assert not tickets, "requests left unfinished"
+    for i, (p, n) in enumerate(reqs):
+        A = _alone(lbm, p, n, "fp32_shifted")
+        d = tuple(rel(got[i][k], A[k]) for k in ("eta", "p", "sigma"))
+        _say("served mixed references", i, p.nx, p.ny, d)
+        assert max(d) < 1e-6, (i, d)
+
+
 def test_admission_is_bounded_by_pool_memory(lbm):
     """A pool that holds two of the requests at a time: at most two run, the
     others wait in the queue, and every result still equals the lone solve
