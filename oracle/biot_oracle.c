@@ -85,6 +85,7 @@ typedef struct {
     const double *el_value[4];    /* 2 per boundary cell */
     const double *p_value[4];     /* 1 per boundary cell */
     int32_t pressure_gradient;    /* 0: eq. pressure:gradient, 1: eq. pressure:gradient:alternative */
+    int32_t cycle;                /* 0: V-cycle (Algorithm 4), 1: W-cycle, 2: F-cycle */
 } or_problem;
 
 typedef struct {
@@ -120,6 +121,7 @@ typedef struct {
     int *ne_hist; double *ratio_hist; int hist_cap;
     const int *ne_sched; int ne_sched_len;
     int threads;
+    long coarsest_visits;    /* coarsest-level solves so far (cycle-shape pins) */
 } or_state;
 
 /* ---------------------------------------------------------------- helpers */
@@ -358,10 +360,21 @@ static void smooth(const or_state *o, level_t *lv, double *g, const double *r, c
     for (int c = 0; c < 8 * lv->n; ++c) g[c] = (1.0 - o->gamma) * g[c] + o->gamma * lv->S[c];
 }
 
-/* ELASTIC_MULTIGRID (Algorithm 4) on level l; g is updated in place */
-static void elastic_mg(or_state *o, int l, double *g, const double *r, const double *Ft)
+/* ELASTIC_MULTIGRID (Algorithm 4) on level l; g is updated in place.
+ *
+ * cyc selects how often the coarse correction visits level l - 1.  The paper
+ * gives the V-cycle (one visit) and names W- and F-cycles as future work
+ * without defining them; these follow the textbook recursions:
+ *   V: one V-visit;
+ *   W: two W-visits, the second continuing from the first's coarse iterate
+ *      with the same coarse right-hand side;
+ *   F: an F-visit, then a V-visit continuing from its result.
+ * On the coarsest level (no recursion) every shape is the same 2K sweeps. */
+enum { CYC_V = 0, CYC_W = 1, CYC_F = 2 };
+static void elastic_mg(or_state *o, int l, double *g, const double *r, const double *Ft, int cyc)
 {
     level_t *lv = &o->lv[l];
+    if (l == 1) ++o->coarsest_visits;
     for (int k = 0; k < o->K; ++k) smooth(o, lv, g, r, Ft);
     if (l > 1) {
         level_t *lc = &o->lv[l - 1];
@@ -376,7 +389,8 @@ static void elastic_mg(or_state *o, int l, double *g, const double *r, const dou
             }
         /* coarse correction from zero with the coarse residual, no explicit force */
         memset(lc->g, 0, sizeof(double) * 8 * lc->n);
-        elastic_mg(o, l - 1, lc->g, lc->r, NULL);
+        elastic_mg(o, l - 1, lc->g, lc->r, NULL, cyc);
+        if (cyc != CYC_V) elastic_mg(o, l - 1, lc->g, lc->r, NULL, cyc == CYC_W ? CYC_W : CYC_V);
         /* prolongation P = R^T: every fine cell takes its coarse cell's value */
         for (int y = 0; y < lv->ny; ++y)
             for (int x = 0; x < lv->nx; ++x) {
@@ -533,7 +547,8 @@ or_state *or_create(const or_problem *pb, int *err)
     *err = OR_ERR_ARG;
     if (pb->nx < 1 || pb->ny < 1 || pb->dx <= 0 || pb->dt <= 0 || pb->c0 <= 0 || pb->mu <= 0 ||
         pb->lambda + pb->mu <= 0 || pb->alpha < 0 || pb->alpha > 1 || pb->r < 0 || pb->r > 1 ||
-        pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1 || pb->pressure_gradient < 0 || pb->pressure_gradient > 1)
+        pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1 || pb->pressure_gradient < 0 || pb->pressure_gradient > 1 ||
+        pb->cycle < 0 || pb->cycle > 2)
         return NULL;
     for (int s = 0; s < 4; ++s) if (pb->el_type[s] < 0 || pb->el_type[s] > 3) return NULL;
     if ((pb->el_type[LEFT] == EL_PERIODIC) != (pb->el_type[RIGHT] == EL_PERIODIC)) return NULL;
@@ -698,7 +713,7 @@ static int one_step(or_state *o)
     int j = 0;
     double ratio = -1.0;
     if (ne_fixed > 0) {
-        for (j = 0; j < ne_fixed; ++j) elastic_mg(o, o->L, o->g, NULL, o->Ft);
+        for (j = 0; j < ne_fixed; ++j) elastic_mg(o, o->L, o->g, NULL, o->Ft, o->pb.cycle);
     } else {
         /* adaptive: before each cycle the residual of the current iterate is
          * compared with the iterate itself (stop when ||g - S(g)|| <= tol ||g||,
@@ -711,7 +726,7 @@ static int one_step(or_state *o)
             if (!isfinite(nr)) break;
             if (j >= 1 && nr <= o->pb.ne_tol * ng) break;
             if (j >= o->pb.ne_max) break;
-            elastic_mg(o, o->L, o->g, NULL, o->Ft);
+            elastic_mg(o, o->L, o->g, NULL, o->Ft, o->pb.cycle);
             ++j;
         }
     }
@@ -849,11 +864,14 @@ int or_mg_cycle(or_state *o, int l, double *g, const double *r, const double *Ft
     double *fa = malloc(sizeof(double) * 2 * m);
     planes_to_aos(g, ga, m, 8); planes_to_aos(r, ra, m, 8); planes_to_aos(Ft, fa, m, 2);
     /* the recursion uses the level's own g buffer; work on a private copy */
-    elastic_mg(o, l, ga, r ? ra : NULL, Ft ? fa : NULL);
+    elastic_mg(o, l, ga, r ? ra : NULL, Ft ? fa : NULL, o->pb.cycle);
     aos_to_planes(ga, g, m, 8);
     free(ga); free(ra); free(fa);
     return OR_OK;
 }
+
+/* coarsest-level solves since creation */
+long or_coarsest_visits(const or_state *o) { return o->coarsest_visits; }
 
 /* level sizes */
 int or_level_shape(const or_state *o, int l, int *nx, int *ny)

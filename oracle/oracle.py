@@ -42,7 +42,7 @@ class _Problem(C.Structure):
                 ("ne_tol", C.c_double), ("ne_max", C.c_int32),
                 ("el_type", C.c_int32 * 4), ("flow_type", C.POINTER(C.c_int8) * 4),
                 ("el_value", C.POINTER(C.c_double) * 4), ("p_value", C.POINTER(C.c_double) * 4),
-                ("pressure_gradient", C.c_int32)]
+                ("pressure_gradient", C.c_int32), ("cycle", C.c_int32)]
 
 
 _lib = None
@@ -73,6 +73,8 @@ def _load():
         lib.or_level_shape.argtypes = [vp, C.c_int, ip, ip]
         lib.or_flow_step.argtypes = [vp, dp]
         lib.or_default_levels.argtypes = [C.c_int, C.c_int]
+        lib.or_coarsest_visits.restype = C.c_long
+        lib.or_coarsest_visits.argtypes = [vp]
         _lib = lib
     return _lib
 
@@ -111,6 +113,7 @@ class Oracle:
         pb.r, pb.levels, pb.K, pb.gamma = p.r, p.levels, p.K, p.gamma
         pb.ne_fixed, pb.ne_tol, pb.ne_max = p.ne_fixed, p.ne_tol, p.ne_max
         pb.pressure_gradient = int(getattr(p, "pressure_gradient", 0))
+        pb.cycle = int(getattr(p, "cycle", 0))
         for s in range(4):
             side = p.sides[s]
             fl = np.ascontiguousarray(side.flow, dtype=np.int8)
@@ -226,6 +229,10 @@ class Oracle:
         if rc != OR_OK:
             raise OracleError(rc, "mg_cycle")
         return g
+
+    def coarsest_visits(self):
+        """Coarsest-level solves since creation (2K sweeps each)."""
+        return int(self._lib.or_coarsest_visits(self._h))
 
     def flow_step(self, s_lat):
         s = np.ascontiguousarray(s_lat, dtype=np.float64)

@@ -41,6 +41,9 @@ PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32,
 # populations (eq. pressure:gradient) or the central difference of the pressure
 # (eq. pressure:gradient:alternative)
 GRAD_MOMENTS, GRAD_CENTRAL = 0, 1
+# multigrid cycle shape: the V-cycle of Algorithm 4; W- and F-cycles (named as
+# future work in the conclusion) in their textbook form
+CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
 
 
 @dataclasses.dataclass
@@ -89,6 +92,7 @@ class Problem:
     ne_max: int = 50
     name: str = ""
     pressure_gradient: int = 0         # GRAD_MOMENTS or GRAD_CENTRAL
+    cycle: int = 0                     # CYCLE_V, CYCLE_W or CYCLE_F
 
     # ---- helpers ---------------------------------------------------------
     @property
