@@ -55,6 +55,18 @@ typedef enum {
  * coarsest multigrid level are FP64 in every mode. */
 typedef enum { BP_FP64 = 0, BP_FP32 = 1, BP_FP32_SHIFTED = 2, BP_FP64_SHIFTED = 3 } bp_precision;
 
+/* shape of the multigrid cycle.  The paper gives the V-cycle (Algorithm 4:
+ * one visit of the coarser level per cycle) and names W- and F-cycles as
+ * future work (Sec. 5) without defining them; they take the textbook form:
+ * W visits the coarser level twice, F makes an F-visit and then a V-visit,
+ * the second visit continuing from the first's coarse iterate with the same
+ * restricted right-hand side.  W- and F-cycles sweep every level with the
+ * tile kernels (the one-workgroup coarse tail runs V-cycles), and a cycle on
+ * L levels solves the coarsest 2^(L-1) (W) or L (F) times, so they pay off
+ * only on shallow hierarchies.  A batch takes one shape; the server runs
+ * V-cycles. */
+typedef enum { BP_CYCLE_V = 0, BP_CYCLE_W = 1, BP_CYCLE_F = 2 } bp_cycle;
+
 /* flow boundary types (Sec. 3.6): periodic, pressure Dirichlet (halfway
  * anti-bounce-back, eq. BC:pressure), no flow (halfway bounce-back,
  * eq. BC:noFlow), symmetry (mirror reflection; impermeable) */
@@ -103,6 +115,8 @@ typedef struct {
                                flow populations (eq. pressure:gradient), 1 = central
                                difference of p (eq. pressure:gradient:alternative); both
                                add half the central gradient of the source */
+  int32_t cycle;            /* bp_cycle: shape of the multigrid cycle (0 = the V-cycle of
+                               Algorithm 4) */
 } bp_problem;
 
 typedef struct bp_solver bp_solver;

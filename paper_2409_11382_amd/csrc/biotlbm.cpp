@@ -88,6 +88,7 @@ bp_status validate(const bp_problem* p) {
   if (p->K < 1) return fail(BP_ERR_ARG, "K must be >= 1");
   if (p->pressure_gradient != 0 && p->pressure_gradient != 1)
     return fail(BP_ERR_ARG, "pressure_gradient must be 0 (first moments) or 1 (central difference)");
+  if (p->cycle < BP_CYCLE_V || p->cycle > BP_CYCLE_F) return fail(BP_ERR_ARG, "cycle must be V (0), W (1) or F (2)");
   if (p->ne_fixed < 0) return fail(BP_ERR_ARG, "ne_fixed must be >= 0");
   if (p->ne_fixed == 0 && (!(p->ne_tol > 0) || p->ne_max < 1))
     return fail(BP_ERR_ARG, "adaptive mode needs ne_tol > 0 and ne_max >= 1");
@@ -133,6 +134,7 @@ struct Layout {
   int L = 1, nx = 0, ny = 0, pitch = 0;
   int64_t plane = 0;
   bool fdbl = true, shift = false, ref64 = true;
+  int cycle = BP_CYCLE_V;
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
   size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_elbc[4], off_ftype[4], off_flbc[4];
@@ -146,6 +148,7 @@ struct Layout {
 int tail_depth_of(const Layout& lo) {
   if (const char* e = std::getenv("BIOT_NO_TAIL"))
     if (std::atoi(e) != 0) return 0;
+  if (lo.cycle != BP_CYCLE_V) return 0;  // the tail kernel runs V-cycles
   for (int l = lo.L - 1; l >= 1; --l) {
     const LevelLay& v = lo.lv[l];
     const int cap = v.dbl ? kTailCellsF64 : kTailCellsF32;
@@ -162,6 +165,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.plane = (int64_t)lo.pitch * p->ny;
   lo.fdbl = (p->prec == BP_FP64 || p->prec == BP_FP64_SHIFTED);
   lo.shift = (p->prec == BP_FP32_SHIFTED || p->prec == BP_FP64_SHIFTED);
+  lo.cycle = p->cycle;
   const size_t fs = lo.fdbl ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -598,6 +602,7 @@ struct Engine {
   bool fdbl = true, shift = false;
   bool ref64 = false;  // shifted storage: some problem keeps FP64 references
   int K = 4, ne = 3, maxL = 1;
+  int cycle = BP_CYCLE_V;  // cycle shape of every problem
   std::vector<Prob*> probs;
   // engine area (device): descriptors, tile lists, problem ids
   char* area = nullptr;
@@ -837,8 +842,9 @@ int smoothing_launches(int count, bool quad, bool fuse) {
 // smoothing applications per launch (after a separate first sweep only where
 // the launch count keeps the iterate ending in A).
 void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true,
-                bool fuse = false) {
+                bool fuse = false, int cyc = -1, bool from_zero = true) {
   if (d >= E.maxL) return;
+  if (cyc < 0) cyc = E.cycle;
   const int full = tail ? 0 : 2, restr = full + 1;
   if (tail && E.depth[d].tail_cnt > 0) {
     Op o;
@@ -868,11 +874,17 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
     sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, fuse_here, deeper && E.depth[d].fres,
                         &restricted);
   } else {
-    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0, false, false, fuse, deeper && E.depth[d].fres, &restricted);
+    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0 && from_zero, false, false, fuse, deeper && E.depth[d].fres,
+                        &restricted);
   }
   if (deeper) {
     if (!restricted) add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
-    add_vcycle(E, ops, d + 1, false, false, tail, fuse);
+    // the coarse correction: one V-visit; W: two W-visits, F: an F-visit then
+    // a V-visit, the second continuing from the first's iterate (buffer A)
+    // with the same restricted right-hand side
+    add_vcycle(E, ops, d + 1, false, false, tail, fuse, cyc, true);
+    if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_W, false);
+    if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_V, false);
   }
   add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse_here);
 }
@@ -1060,7 +1072,7 @@ bp_status build_graph(Engine& E) {
 }
 
 bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap, size_t tiles_cap, hipStream_t st,
-                      bool fdbl, bool shift, int K, int ne) {
+                      bool fdbl, bool shift, int K, int ne, int cycle = BP_CYCLE_V) {
   E.stream = st;
   E.area = area;
   E.area_bytes = area_bytes;
@@ -1073,6 +1085,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   E.shift = shift;
   E.K = K;
   E.ne = ne;
+  E.cycle = cycle;
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
@@ -1531,7 +1544,8 @@ bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void*
   hipStream_t st = (hipStream_t)hip_stream;
   char* w = (char*)device_ws;
   s->ws = w;
-  bp_status rc = engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed);
+  bp_status rc =
+      engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed, p->cycle);
   if (rc == BP_OK) rc = setup_problem(p, lo, w, st, s->P);
   if (rc == BP_OK) {
     s->E.probs = {&s->P};
@@ -1731,7 +1745,9 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
     }
     if (level > 1) {
       add_sweeps(E, ops, d, 3, kRestrict, sel, 0, 0, 0);
-      add_vcycle(E, ops, d + 1, false, false, false);
+      add_vcycle(E, ops, d + 1, false, false, false, false, E.cycle, true);
+      if (E.cycle == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, false, false, BP_CYCLE_W, false);
+      if (E.cycle == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, false, false, BP_CYCLE_V, false);
     }
     for (int k = 0; k < E.K; ++k) {
       add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);
@@ -1883,8 +1899,9 @@ bp_status bp_batch_workspace_bytes(const bp_problem* probs, int32_t n, size_t* d
   size_t total = 0, te = 0;
   for (int i = 0; i < n; ++i) {
     BPCHK(validate(&probs[i]));
-    if (probs[i].prec != probs[0].prec || probs[i].K != probs[0].K || probs[i].ne_fixed != probs[0].ne_fixed)
-      return fail(BP_ERR_ARG, "a batch needs one precision, one K and one fixed V-cycle count");
+    if (probs[i].prec != probs[0].prec || probs[i].K != probs[0].K || probs[i].ne_fixed != probs[0].ne_fixed ||
+        probs[i].cycle != probs[0].cycle)
+      return fail(BP_ERR_ARG, "a batch needs one precision, one K, one cycle shape and one fixed cycle count");
     if (probs[i].ne_fixed < 1) return fail(BP_ERR_ARG, "batched problems need a fixed V-cycle count");
     Layout lo;
     make_layout(&probs[i], lo);
@@ -1915,7 +1932,7 @@ bp_status bp_batch_create(const bp_problem* probs, int32_t n, void* device_ws, s
   }
   for (int i = 0; i < n; ++i) off += los[i].total;
   bp_status rc = engine_init(b->E, w + off, need - off, (size_t)n, te, st, los[0].fdbl, los[0].shift, probs[0].K,
-                             probs[0].ne_fixed);
+                             probs[0].ne_fixed, probs[0].cycle);
   off = 0;
   for (int i = 0; i < n && rc == BP_OK; ++i) {
     rc = setup_problem(&probs[i], los[i], w + off, st, b->P[i]);
@@ -2017,6 +2034,7 @@ bp_status bp_server_submit(bp_server* s, const bp_problem* p, int32_t nsteps, in
   BPCHK(validate(p));
   if (p->prec != s->prec || p->K != s->K || p->ne_fixed != s->ne)
     return fail(BP_ERR_ARG, "a request must use the server's precision, K and fixed V-cycle count");
+  if (p->cycle != BP_CYCLE_V) return fail(BP_ERR_ARG, "the server runs V-cycles");
   auto r = std::make_unique<SrvReq>();
   make_layout(p, r->lo);
   r->tiles = tile_entries_for(r->lo);

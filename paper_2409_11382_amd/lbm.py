@@ -39,7 +39,8 @@ class _Problem(C.Structure):
                 ("body_f", C.POINTER(C.c_double)), ("source_s", C.POINTER(C.c_double)),
                 ("r", C.c_double), ("levels", C.c_int32), ("K", C.c_int32), ("gamma", C.c_double),
                 ("ne_fixed", C.c_int32), ("ne_tol", C.c_double), ("ne_max", C.c_int32),
-                ("side", _Side * 4), ("prec", C.c_int32), ("pressure_gradient", C.c_int32)]
+                ("side", _Side * 4), ("prec", C.c_int32), ("pressure_gradient", C.c_int32),
+                ("cycle", C.c_int32)]
 
 
 class _Tuning(C.Structure):
@@ -181,6 +182,7 @@ def marshal_problem(p: Problem, prec="fp64"):
         pb.side[s].p_value = _dptr(pv)
     pb.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     pb.pressure_gradient = int(p.pressure_gradient)
+    pb.cycle = int(p.cycle)
     return pb, keep
 
 

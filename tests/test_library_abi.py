@@ -57,7 +57,8 @@ def test_degenerate_problems_are_rejected_on_the_host():
     base = P.loaded_strip(n=64)
     bad = [dict(nx=0), dict(ny=0), dict(dt=0.0), dict(dx=-1.0), dict(alpha=nan), dict(mu=nan),
            dict(gamma=1.5), dict(ne_fixed=0, ne_tol=0.0), dict(ne_fixed=0, ne_tol=1e-6, ne_max=0),
-           dict(pressure_gradient=2), dict(levels=7),          # 64 / 2^6 = 1 cell on the coarsest level
+           dict(pressure_gradient=2), dict(cycle=3), dict(cycle=-1),
+           dict(levels=7),                                     # 64 / 2^6 = 1 cell on the coarsest level
            dict(nx=63, levels=2)]                              # odd width cannot coarsen
     for kw in bad:
         with pytest.raises(L.BiotError) as ei:
@@ -73,6 +74,11 @@ def test_degenerate_problems_are_rejected_on_the_host():
     pb, kb = L.marshal_problem(base, "fp64")
     arr = (L._Problem * 2)(pa, pb)
     assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # one precision per batch
+    pw, kw_ = L.marshal_problem(base.replace(cycle=P.CYCLE_W), "fp32_shifted")
+    arr = (L._Problem * 2)(pa, pw)
+    assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # one cycle shape per batch
+    arr = (L._Problem * 2)(pw, pw)
+    assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_OK
     del ka, kb
 
 
