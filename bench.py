@@ -182,12 +182,12 @@ def fp64_alone_ms_per_step(p, steps=5):
     return 1e3 * ev / steps
 
 
-def terzaghi(steps=200):
+def terzaghi(steps=200, cycle=0):
     """Terzaghi 8 x 128 (3 levels), adaptive N_E to 1e-8, FP64: all 200 steps
-    from t = 0."""
+    from t = 0 (cycle: shape of the multigrid cycle)."""
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
-    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50)
+    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50).replace(cycle=cycle)
     s = lbm.Solver(p, "fp64")
     t0 = time.perf_counter()
     s.step(steps)
@@ -198,6 +198,30 @@ def terzaghi(steps=200):
     return {"steps": steps, "ms_per_step": round(1e3 * wall / steps, 4),
             "mlups": round(p.ncells * steps / wall / 1e6, 4), "mean_ne": round(st["total_cycles"] / steps, 2),
             "levels": st["levels"]}
+
+
+def cycle_shapes(n=512, steps=5):
+    """V-, W- and F-cycles on the loaded strip n x n in FP32 shifted storage,
+    adaptive to ||g - S(g)|| <= 1e-6 ||g|| (at most 30 cycles): milliseconds
+    per step and mean cycles per step, after two untimed steps."""
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    out = {}
+    for name, cyc in (("V", P.CYCLE_V), ("W", P.CYCLE_W), ("F", P.CYCLE_F)):
+        p = P.loaded_strip(n=n, alpha=1.0, ne_fixed=0, ne_tol=1e-6, ne_max=30).replace(cycle=cyc)
+        s = lbm.Solver(p, "fp32_shifted")
+        s.step(2)
+        s.fields()
+        c0 = s.stats()["total_cycles"]
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.fields()  # synchronises
+        wall = time.perf_counter() - t0
+        cycles = s.stats()["total_cycles"] - c0
+        s.close()
+        out[name] = {"ms_per_step": round(1e3 * wall / steps, 3), "mean_cycles": round(cycles / steps, 2),
+                     "ms_per_cycle": round(1e3 * wall / cycles, 3)}
+    return out
 
 
 def speedups_over_fp64_alone(batch, rate, count):
@@ -379,6 +403,10 @@ def main():
                                      for r in (2.0, 10.0, 20.0)]
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
         out["terzaghi_8x128"] = terzaghi()
+        out["cycle_shapes"] = {"terzaghi_8x128_fp64": {"V": out["terzaghi_8x128"],
+                                                       "W": terzaghi(cycle=P.CYCLE_W),
+                                                       "F": terzaghi(cycle=P.CYCLE_F)},
+                               "loaded_strip_%d_fp32_shifted" % args.n: cycle_shapes(args.n)}
         out["speedups_over_fp64_alone"] = speedups_over_fp64_alone(out["batched"], args.serve_rate,
                                                                    args.serve_count)
     if not args.no_cpu:
