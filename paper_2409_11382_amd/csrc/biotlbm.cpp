@@ -148,7 +148,6 @@ struct Layout {
 int tail_depth_of(const Layout& lo) {
   if (const char* e = std::getenv("BIOT_NO_TAIL"))
     if (std::atoi(e) != 0) return 0;
-  if (lo.cycle != BP_CYCLE_V) return 0;  // the tail kernel runs V-cycles
   for (int l = lo.L - 1; l >= 1; --l) {
     const LevelLay& v = lo.lv[l];
     const int cap = v.dbl ? kTailCellsF64 : kTailCellsF32;
@@ -853,6 +852,8 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
     o.tl.pids = (const int*)(E.d_tiles + E.depth[d].tail_off);
     o.tl.depth = d;
     o.tl.K = E.K;
+    o.tl.shape = cyc;
+    o.tl.from_zero = from_zero ? 1 : 0;
     o.count = E.depth[d].tail_cnt;
     ops.push_back(o);
   }

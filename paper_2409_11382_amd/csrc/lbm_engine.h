@@ -114,7 +114,11 @@ struct TailL {
   const int* skip;  // as in SweepL
   int depth;       // depth of the tail's top level
   int K;           // smoothing steps
+  int shape;       // cycle shape of this visit of the top level: 0 V, 1 W, 2 F
+  int from_zero;   // the top level's iterate starts at zero (else from its buffer A)
 };
+// deepest top level a cycle-shaped tail handles (levels 1..kTailMaxLevel)
+constexpr int kTailMaxLevel = 15;
 
 template <typename T, typename Tc, int MODE, bool SHIFT>
 hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);

@@ -1628,6 +1628,189 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
   }
 }
 
+// ---- cycle-shaped tail: W- and F-visits, and visits that continue from the
+// top level's stored iterate.  The recursion of the cycle runs as a loop over
+// an explicit per-level stack whose entries are the same for every thread, so
+// every barrier is reached by the whole workgroup.  Between levels a thread
+// passes only its own cells through global memory (iterate in buffer A,
+// right-hand side in r); the coarse correction that finer cells read from
+// other threads passes through LDS, as in tail_run.
+
+// the coarse result handed to the finer level: plane q of cell c at
+// lds + n + q n in the level's type (n: the level's cells)
+template <typename TT>
+__device__ __forceinline__ void tail_hand_up(char* lds, int n, const TT (&G)[1][8]) {
+  const int c = threadIdx.x;
+  TT* sG = (TT*)lds + n;
+  __syncthreads();  // every pull of the last sweep has read sG
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
+  }
+  __syncthreads();
+}
+
+// pre-smoothing of level l >= 2 (K sweeps from zero or from buffer A), the
+// iterate stored to A, the residual restricted into level l - 1's r
+template <typename T, typename T1>
+__device__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[l];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[1];
+  T G[1][8], R[1][8];
+  tail_tab_load(P, l, c, tb);
+  tail_load1<T>(V, V.r, c, R);
+  if (zero)
+    tail_zero(G);
+  else
+    tail_load1<T>(V, V.gA, c, G);
+  for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
+  tail_store1<T>(V, V.gA, c, G);
+  tail_relax<T, 1>(k, n, tb, G, R, sD, sG, false);
+  __syncthreads();  // every pull has read sG
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
+  }
+  __syncthreads();
+  const LevelD& C = P.lv[l - 1];
+  const int cnx = nx / 2, cn = cnx * (ny / 2);
+  T sum[8];
+  if (c < cn) {
+    const int X = c % cnx, Y = c / cnx;
+    const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum[q] = (sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum[q] = T(0);
+  }
+  if (l - 1 >= 2) {
+    T Rc[1][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Rc[0][q] = sum[q];
+    tail_store1<T>(C, C.r, c, Rc);
+  } else {
+    T1 Rc[1][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Rc[0][q] = T1(sum[q]);
+    tail_store1<T1>(C, C.r, c, Rc);
+  }
+  __syncthreads();  // sG is reused by the next level
+}
+
+// the coarsest level: 2K sweeps from zero or from buffer A, stored to A and
+// handed up through LDS
+template <typename T1>
+__device__ void tail_coarsest(const ProbD& P, int K, bool zero, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[1];
+  const int n = V.nx * V.ny;
+  T1* sD = (T1*)lds;
+  T1* sG = sD + n;
+  const ElConst<T1> k = tail_consts<T1>(P);
+  TailTab tb[1];
+  T1 G[1][8], R[1][8];
+  tail_tab_load(P, 1, c, tb);
+  tail_load1<T1>(V, V.r, c, R);
+  if (zero)
+    tail_zero(G);
+  else
+    tail_load1<T1>(V, V.gA, c, G);
+  for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G, R, sD, sG, true);
+  tail_store1<T1>(V, V.gA, c, G);
+  tail_hand_up<T1>(lds, n, G);
+}
+
+// post-smoothing of level l >= 2: its stored iterate plus the injected coarse
+// correction (in LDS, type TC), K sweeps, stored to A and handed up
+template <typename T, typename TC>
+__device__ void tail_post(const ProbD& P, int l, int K, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[l];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  const int cn = (nx / 2) * (ny / 2);
+  TailTab tb[1];
+  T G[1][8], R[1][8];
+  tail_tab_load(P, l, c, tb);
+  tail_load1<T>(V, V.gA, c, G);
+  tail_load1<T>(V, V.r, c, R);
+  if (c < n) {
+    const int ci = ((c / nx) >> 1) * (nx / 2) + ((c % nx) >> 1);
+    const TC* ex = (const TC*)lds + cn;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[0][q] += T(ex[q * cn + ci]);
+  }
+  __syncthreads();  // the sweeps' sD overlaps the coarse result just read
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
+  tail_store1<T>(V, V.gA, c, G);
+  tail_hand_up<T>(lds, n, G);
+}
+
+// one visit of shape `shape` of levels lt..1: V one coarse visit, W two
+// W-visits, F an F-visit then a V-visit; every coarse visit after the first
+// continues from the coarse level's stored iterate
+template <typename T, typename T1>
+__device__ void tail_run_shaped(const ProbD& P, int lt, int K, int shape, bool zero, char* lds) {
+  // per level: the shape of its current visit (2 bits at 2 l) and whether a
+  // second coarse visit is still to start (bit l); uniform over the workgroup
+  uint32_t shp = uint32_t(shape) << (2 * lt), second = 0;
+  auto shape_of = [&](int lv) { return int((shp >> (2 * lv)) & 3u); };
+  auto set_shape = [&](int lv, int v) { shp = (shp & ~(3u << (2 * lv))) | (uint32_t(v) << (2 * lv)); };
+  int l = lt;
+  bool z = zero, entering = true;
+  for (;;) {
+    if (entering) {
+      if (l == 1) {
+        tail_coarsest<T1>(P, K, z, lds);
+        if (lt == 1) break;
+        l = 2;
+        entering = false;
+        continue;
+      }
+      tail_pre<T, T1>(P, l, K, z, lds);
+      const int sh = shape_of(l);
+      if (sh != 0) second |= 1u << l;  // W and F visit the coarser level twice
+      set_shape(l - 1, sh);            // the first visit: W-, F- or V-visit as this one
+      --l;
+      z = true;
+      continue;
+    }
+    // back on level l from a visit of level l - 1
+    if (second & (1u << l)) {
+      second &= ~(1u << l);
+      set_shape(l - 1, shape_of(l) == 1 ? 1 : 0);  // W: another W-visit; F: a V-visit
+      --l;
+      z = false;  // continuing from the first visit's iterate
+      entering = true;
+      continue;
+    }
+    if (l == 2)
+      tail_post<T, T1>(P, l, K, lds);
+    else
+      tail_post<T, T>(P, l, K, lds);
+    if (l == lt) break;
+    ++l;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_shaped(TailL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
+  extern __shared__ char lds[];
+  const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
+  const int lt = P.L - a.depth;
+  if (lt < 1 || lt > kTailMaxLevel) return;  // uniform; the host never asks for it
+  tail_run_shaped<T, double>(P, lt, a.K, a.shape, a.from_zero != 0, lds);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
   if (a.skip && *a.skip) return;  // uniform over the grid
@@ -1640,15 +1823,22 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
   if (nprobs <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kTailLdsBytes);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kTailLdsBytes);
-    if (e != hipSuccess) return e;
+    const void* ks[4] = {(const void*)k_tail<float>, (const void*)k_tail<double>, (const void*)k_tail_shaped<float>,
+                         (const void*)k_tail_shaped<double>};
+    for (const void* kf : ks) {
+      const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, kTailLdsBytes);
+      if (e != hipSuccess) return e;
+    }
     attr = true;
   }
-  if (dbl)
+  // the V-cycle from a zero iterate (the time step's own visit) takes the
+  // prefetching kernel; other shapes and continued visits the shaped one
+  const bool shaped = a.shape != 0 || !a.from_zero;
+  if (shaped && dbl)
+    hipLaunchKernelGGL(k_tail_shaped<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  else if (shaped)
+    hipLaunchKernelGGL(k_tail_shaped<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  else if (dbl)
     hipLaunchKernelGGL(k_tail<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
   else
     hipLaunchKernelGGL(k_tail<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
