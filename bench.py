@@ -105,6 +105,18 @@ def time_steps(solver, steps, warmup):
     return wall, ev0.elapsed_time(ev1) / 1e3
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
     """The FP64 oracle on the host's cores, on a bounded number of steps of the
     same workload."""
@@ -120,6 +132,7 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
     o.step(n)
     dt = time.perf_counter() - t0
     out = {"value": round(problem.ncells * n / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
            "sample": f"{n} coupled steps of the same {problem.nx}x{problem.ny} workload after 1 untimed step, "
                      f"FP64 C oracle, {threads} OpenMP threads"}
     if threads > 1:  # and on one core, a smaller sample
@@ -400,7 +413,7 @@ def main():
         out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
         keys = ("rate_per_s", "requests", "solves_per_s", "p50_latency_s", "p99_latency_s", "mlups", "peak_active")
         out["serving_rate_sweep"] = [{k: v for k, v in serve.simulate(rate=r, count=12, seed=3).items() if k in keys}
-                                     for r in (2.0, 10.0, 20.0)]
+                                     for r in (2.0, 10.0, 20.0, 50.0)]
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
         out["terzaghi_8x128"] = terzaghi()
         out["cycle_shapes"] = {"terzaghi_8x128_fp64": {"V": out["terzaghi_8x128"],
