@@ -135,9 +135,10 @@ struct Layout {
   int64_t plane = 0;
   bool fdbl = true, shift = false, ref64 = true;
   int cycle = BP_CYCLE_V;
+  bool full_tail = false;    // the whole problem fits one workgroup (adaptive cycles)
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
-  size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_elbc[4], off_ftype[4], off_flbc[4];
+  size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_addt, off_elbc[4], off_ftype[4], off_flbc[4];
   int ntiles_fine = 0, ntiles_fine2 = 0;
   int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
   size_t total = 0;
@@ -219,11 +220,20 @@ void make_layout(const bp_problem* p, Layout& lo) {
       lo.ntiles_fine2 = std::max(lo.ntiles_fine2, sweepn_tiles(p->nx, p->ny, lo.fdbl, A, lo.shift, alt && A == 2));
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(64);
-  // gather tables of the coarse tail's levels (8 words per cell, level 1 first)
+  // a problem whose finest level fits the tail kernel, with the coarse tail
+  // right below it, runs each adaptive cycle after the stopping test in one
+  // workgroup (unshifted storage; BIOT_NO_FULL_TAIL=1 switches it off)
+  lo.full_tail = !lo.shift && lo.L >= 2 && lo.tail_depth == 1 && lo.L - 1 <= kTailMaxLevel &&
+                 (int64_t)p->nx * p->ny <= (lo.fdbl ? kTailCellsF64 : kTailCellsF32);
+  if (const char* e = std::getenv("BIOT_NO_FULL_TAIL"))
+    if (std::atoi(e) != 0) lo.full_tail = false;
+  // gather tables of the coarse tail's levels (8 words per cell, level 1
+  // first), and of the finest level for the whole-problem tail
   size_t tcells = 0;
   if (lo.tail_depth > 0)
-    for (int l = 1; l <= lo.L - lo.tail_depth; ++l) tcells += (size_t)lo.lv[l].nx * lo.lv[l].ny;
+    for (int l = 1; l <= (lo.full_tail ? lo.L : lo.L - lo.tail_depth); ++l) tcells += (size_t)lo.lv[l].nx * lo.lv[l].ny;
   lo.off_ttab = take(tcells * 8 * sizeof(uint32_t));
+  lo.off_addt = lo.full_tail ? take(8 * lo.plane * fs) : SIZE_MAX;
   for (int s = 0; s < 4; ++s) {
     const int n = side_len(s, p->nx, p->ny);
     lo.off_elbc[s] = take((size_t)n * 8 * 8);
@@ -491,7 +501,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   HIPCHK(launch_fill_zero(base, lo.total, st));
   if (lo.tail_depth > 0) {
     size_t o = 0;
-    for (int l = 1; l <= lo.L - lo.tail_depth; ++l) {
+    for (int l = 1; l <= (lo.full_tail ? lo.L : lo.L - lo.tail_depth); ++l) {
       HIPCHK(launch_tail_tables(d.el, lo.lv[l].nx, lo.lv[l].ny, d.ttab + o, st));
       o += (size_t)8 * lo.lv[l].nx * lo.lv[l].ny;
     }
@@ -513,8 +523,10 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.omf = nullptr;
     d.omf_u = omega_of(p->kappa_uniform);
   }
+  std::vector<double> ets[4];
   for (int k = 0; k < 4; ++k) {
-    std::vector<double> et, ft;
+    std::vector<double>& et = ets[k];
+    std::vector<double> ft;
     std::vector<int8_t> ty;
     elastic_terms(p, k, p->dx, et);
     flow_terms(p, k, ft, ty);
@@ -529,6 +541,49 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
     d.elbc[k] = used ? elbc : nullptr;
     d.ftype[k] = ftype;
     d.flbc[k] = flbc;
+  }
+  d.addt = nullptr;
+  if (lo.full_tail) {
+    // the finest level's wall terms per cell and population, added to the
+    // pulled value by the whole-problem tail: the data of the halfway rule
+    // (Dirichlet or traction) that the pull takes, chosen as the sweeps
+    // choose it (at a corner the y-wall's rule unless that wall is a
+    // symmetry wall; two symmetry walls reflect diagonally, with no data)
+    const int nx = p->nx, ny = p->ny;
+    const bool perx = p->side[BP_LEFT].el == BP_EL_PERIODIC, pery = p->side[BP_BOTTOM].el == BP_EL_PERIODIC;
+    auto data = [&](int side) -> const double* {
+      const int el = p->side[side].el;
+      return (el == BP_EL_DIRICHLET || el == BP_EL_TRACTION) ? ets[side].data() : nullptr;
+    };
+    std::vector<double> add((size_t)8 * N, 0.0);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const bool wl = !perx && x == 0, wr = !perx && x == nx - 1;
+        const bool wb = !pery && y == 0, wt = !pery && y == ny - 1;
+        for (int q = 0; q < 8; ++q) {
+          const int cx = CX8[q], cy = CY8[q];
+          const bool ox = (cx > 0 && wl) || (cx < 0 && wr);
+          const bool oy = (cy > 0 && wb) || (cy < 0 && wt);
+          if (!(ox || oy)) continue;
+          const int elx = p->side[cx > 0 ? BP_LEFT : BP_RIGHT].el;
+          const int ely = p->side[cy > 0 ? BP_BOTTOM : BP_TOP].el;
+          bool usex;
+          if (ox && oy) {
+            if (elx == BP_EL_SYMMETRY && ely == BP_EL_SYMMETRY) continue;
+            usex = ely == BP_EL_SYMMETRY;
+          } else if (ox) {
+            if (elx == BP_EL_SYMMETRY) continue;
+            usex = true;
+          } else {
+            if (ely == BP_EL_SYMMETRY) continue;
+            usex = false;
+          }
+          const double* bc = data(usex ? (cx > 0 ? BP_LEFT : BP_RIGHT) : (cy > 0 ? BP_BOTTOM : BP_TOP));
+          if (bc) add[(size_t)q * N + (size_t)y * nx + x] = bc[8 * (usex ? y : x) + q];
+        }
+      }
+    BPCHK(up(st, lo.fdbl, base + lo.off_addt, nx, ny, lo.pitch, lo.plane, add.data(), 8));
+    d.addt = base + lo.off_addt;
   }
   BPCHK(upload_loads(st, P, p->body_f, p->source_s));
   return BP_OK;
@@ -1159,7 +1214,29 @@ bp_status build_adaptive(Engine& E) {
   if (E.shift) E.ad_ops[AD_START].push_back(cell_op(E, OP_REBASE));
   E.ad_ops[AD_START].push_back(cell_op(E, OP_FORCE));
   E.ad_ops[AD_START].push_back(prob_op(E, OP_AD_RESET));
-  add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
+  // a problem whose finest level fits one workgroup runs each cycle (after
+  // the stopping test) as one whole-problem tail launch; the cycle's result
+  // ends in buffer A as the tile schedule's does
+  const bool full = E.probs.size() == 1 && P.lo.full_tail && E.maxL >= 2 && E.depth[1].tail_cnt == 1;
+  auto full_tail = [&](int fine_in, int fine_pre) {
+    Op o;
+    o.kind = OP_TAIL;
+    o.tl.probs = E.d_probs;
+    o.tl.pids = (const int*)(E.d_tiles + E.depth[1].tail_off);
+    o.tl.depth = 0;
+    o.tl.K = E.K;
+    o.tl.shape = E.cycle;
+    o.tl.from_zero = 0;
+    o.tl.full = 1;
+    o.tl.fine_in = fine_in;
+    o.tl.fine_pre = fine_pre;
+    o.count = 1;
+    return o;
+  };
+  if (full)
+    E.ad_ops[AD_FIRST].push_back(full_tail(0, E.K));
+  else
+    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
   std::vector<Op>& u = E.ad_ops[AD_UNIT];
   if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
   add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);
@@ -1170,7 +1247,10 @@ bp_status build_adaptive(Engine& E) {
   u.push_back(fin);
   set_skip(u, 0, P.d.ad);
   const size_t c0 = u.size();
-  add_vcycle(E, u, 0, true, false, true, E.fuse);
+  if (full)
+    u.push_back(full_tail(1, E.K - 1));  // from the measuring sweep's output (B)
+  else
+    add_vcycle(E, u, 0, true, false, true, E.fuse);
   set_skip(u, c0, P.d.ad);
   E.ad_ops[AD_END].push_back(flow_op(E));
   E.ad_ops[AD_END].push_back(prob_op(E, OP_ADVANCE));

@@ -66,6 +66,8 @@ struct ProbD {
   int grad_central;           // explicit force: central difference of p instead of first moments
   int ntiles_fine2;           // two-application sweep tiles of the finest level
   uint32_t* ttab;             // coarse tail: per-cell gather tables of levels 1.. (8 words per cell)
+  void* addt;                 // whole-problem tail: the finest level's wall terms, 8 planes
+                              // in the population precision (or null)
 };
 
 struct SweepL {
@@ -116,6 +118,10 @@ struct TailL {
   int K;           // smoothing steps
   int shape;       // cycle shape of this visit of the top level: 0 V, 1 W, 2 F
   int from_zero;   // the top level's iterate starts at zero (else from its buffer A)
+  int full;        // the whole problem from its finest level (depth 0), whose iterate
+                   // is read from buffer fine_in (0 A, 1 B) and pre-smoothed fine_pre
+                   // times; the cycle's result ends in A
+  int fine_in, fine_pre;
 };
 // deepest top level a cycle-shaped tail handles (levels 1..kTailMaxLevel)
 constexpr int kTailMaxLevel = 15;

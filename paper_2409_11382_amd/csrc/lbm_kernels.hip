@@ -1653,7 +1653,7 @@ __device__ __forceinline__ void tail_hand_up(char* lds, int n, const TT (&G)[1][
 // pre-smoothing of level l >= 2 (K sweeps from zero or from buffer A), the
 // iterate stored to A, the residual restricted into level l - 1's r
 template <typename T, typename T1>
-__device__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
+__device__ __forceinline__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
   const int c = threadIdx.x;
   const LevelD& V = P.lv[l];
   const int nx = V.nx, ny = V.ny, n = nx * ny;
@@ -1706,7 +1706,7 @@ __device__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
 // the coarsest level: 2K sweeps from zero or from buffer A, stored to A and
 // handed up through LDS
 template <typename T1>
-__device__ void tail_coarsest(const ProbD& P, int K, bool zero, char* lds) {
+__device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, bool zero, char* lds) {
   const int c = threadIdx.x;
   const LevelD& V = P.lv[1];
   const int n = V.nx * V.ny;
@@ -1729,7 +1729,7 @@ __device__ void tail_coarsest(const ProbD& P, int K, bool zero, char* lds) {
 // post-smoothing of level l >= 2: its stored iterate plus the injected coarse
 // correction (in LDS, type TC), K sweeps, stored to A and handed up
 template <typename T, typename TC>
-__device__ void tail_post(const ProbD& P, int l, int K, char* lds) {
+__device__ __forceinline__ void tail_post(const ProbD& P, int l, int K, char* lds) {
   const int c = threadIdx.x;
   const LevelD& V = P.lv[l];
   const int nx = V.nx, ny = V.ny, n = nx * ny;
@@ -1758,7 +1758,7 @@ __device__ void tail_post(const ProbD& P, int l, int K, char* lds) {
 // W-visits, F an F-visit then a V-visit; every coarse visit after the first
 // continues from the coarse level's stored iterate
 template <typename T, typename T1>
-__device__ void tail_run_shaped(const ProbD& P, int lt, int K, int shape, bool zero, char* lds) {
+__device__ __forceinline__ void tail_run_shaped(const ProbD& P, int lt, int K, int shape, bool zero, char* lds) {
   // per level: the shape of its current visit (2 bits at 2 l) and whether a
   // second coarse visit is still to start (bit l); uniform over the workgroup
   uint32_t shp = uint32_t(shape) << (2 * lt), second = 0;
@@ -1801,6 +1801,163 @@ __device__ void tail_run_shaped(const ProbD& P, int lt, int K, int shape, bool z
   }
 }
 
+// ---- whole-problem tail: the finest level too, for problems of at most
+// one workgroup's cells.  Its sweeps add the explicit force to the
+// self-force and its wall terms (per cell and population, scaled like the
+// post-collision populations) to the pulled values; R = 0 there.
+
+// one application of S on the finest level held by the workgroup (one cell
+// per thread): as tail_relax with the force (Fx, Fy) and wall terms `add`
+template <typename T>
+__device__ __forceinline__ void tail_relax_fine(const ElConst<T>& k, int n, const TailTab (&tb)[1], T (&G)[1][8],
+                                                T Fx, T Fy, const T (&add)[8], T* sD, T* sG, bool blend) {
+  const int c = threadIdx.x;
+  if (c < n) sD[c] = k.kD * el_ms(G[0]);
+  __syncthreads();
+  const T sc = blend ? k.gamma : T(1);
+  if (c < n) {
+    T v[3][3];
+    v[0][0] = sD[lo16(tb[0].dn[0])];
+    v[0][1] = sD[hi16(tb[0].dn[0])];
+    v[0][2] = sD[lo16(tb[0].dn[1])];
+    v[1][0] = sD[hi16(tb[0].dn[1])];
+    v[1][2] = sD[lo16(tb[0].dn[2])];
+    v[2][0] = sD[hi16(tb[0].dn[2])];
+    v[2][1] = sD[lo16(tb[0].dn[3])];
+    v[2][2] = sD[hi16(tb[0].dn[3])];
+    v[1][1] = T(0);  // the centred gradient does not use the centre
+    T gx_, gy_;
+    grad_c(v, gx_, gy_);
+    T u[8], s8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = G[0][q];
+    el_collide(u, k.cstar * gx_ + Fx, k.cstar * gy_ + Fy, k, s8, sc);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = s8[q];
+  }
+  __syncthreads();
+  const T omg = T(1) - k.gamma;
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t code = (q & 1) ? hi16(tb[0].pl[q >> 1]) : lo16(tb[0].pl[q >> 1]);
+      const T v = sG[code & 0x7fffu];
+      const T gi = ((code & 0x8000u) ? -v : v) + sc * add[q];
+      G[0][q] = blend ? omg * G[0][q] + gi : G[0][q] - gi;
+    }
+  }
+}
+
+// the finest level's force and wall terms of this thread's cell
+template <typename T>
+__device__ __forceinline__ void tail_fine_terms(const ProbD& P, const LevelD& V, int c, T& Fx, T& Fy, T (&add)[8]) {
+  Fx = Fy = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) add[q] = T(0);
+  if (c >= V.nx * V.ny) return;
+  const int64_t idx = (int64_t)(c / V.nx) * V.pitch + c % V.nx;
+  const T* F = (const T*)P.Ft;
+  const T* ad = (const T*)P.addt;
+  Fx = F[idx];
+  Fy = F[V.plane + idx];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) add[q] = ad[q * V.plane + idx];
+}
+
+// pre-smoothing of the finest level L from buffer A or B (npre sweeps), the
+// iterate stored to A, the residual restricted into level L - 1's r
+template <typename T, typename T1>
+__device__ __forceinline__ void tail_fine_pre(const ProbD& P, int L, int npre, bool from_b, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[L];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[1];
+  T G[1][8], add[8], Fx, Fy;
+  tail_tab_load(P, L, c, tb);
+  tail_load1<T>(V, from_b ? V.gB : V.gA, c, G);
+  tail_fine_terms<T>(P, V, c, Fx, Fy, add);
+  for (int s = 0; s < npre; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, true);
+  tail_store1<T>(V, V.gA, c, G);
+  tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, false);
+  __syncthreads();  // every pull has read sG
+  if (c < n) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
+  }
+  __syncthreads();
+  const LevelD& C = P.lv[L - 1];
+  const int cnx = nx / 2, cn = cnx * (ny / 2);
+  T sum[8];
+  if (c < cn) {
+    const int X = c % cnx, Y = c / cnx;
+    const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum[q] = (sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum[q] = T(0);
+  }
+  if (L - 1 >= 2) {
+    T Rc[1][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Rc[0][q] = sum[q];
+    tail_store1<T>(C, C.r, c, Rc);
+  } else {
+    T1 Rc[1][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Rc[0][q] = T1(sum[q]);
+    tail_store1<T1>(C, C.r, c, Rc);
+  }
+  __syncthreads();  // sG is reused by the coarser levels
+}
+
+// post-smoothing of the finest level: its stored iterate plus the injected
+// coarse correction (in LDS, type TC), K sweeps, stored to A
+template <typename T, typename TC>
+__device__ __forceinline__ void tail_fine_post(const ProbD& P, int L, int K, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[L];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  const int cn = (nx / 2) * (ny / 2);
+  TailTab tb[1];
+  T G[1][8], add[8], Fx, Fy;
+  tail_tab_load(P, L, c, tb);
+  tail_load1<T>(V, V.gA, c, G);
+  tail_fine_terms<T>(P, V, c, Fx, Fy, add);
+  if (c < n) {
+    const int ci = ((c / nx) >> 1) * (nx / 2) + ((c % nx) >> 1);
+    const TC* ex = (const TC*)lds + cn;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) G[0][q] += T(ex[q * cn + ci]);
+  }
+  __syncthreads();  // the sweeps' sD overlaps the coarse result just read
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  for (int s = 0; s < K; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, true);
+  tail_store1<T>(V, V.gA, c, G);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void k_tail_full(TailL a) {
+  if (a.skip && *a.skip) return;  // uniform over the grid
+  extern __shared__ char lds[];
+  const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
+  const int L = P.L;
+  if (L < 2 || L - 1 > kTailMaxLevel || !P.addt) return;  // uniform; the host never asks for it
+  tail_fine_pre<T, double>(P, L, a.fine_pre, a.fine_in != 0, lds);
+  // the coarse correction: one visit, or two for W (W, W) and F (F, V)
+  tail_run_shaped<T, double>(P, L - 1, a.K, a.shape, true, lds);
+  if (a.shape != 0) tail_run_shaped<T, double>(P, L - 1, a.K, a.shape == 1 ? 1 : 0, false, lds);
+  if (L == 2)
+    tail_fine_post<T, double>(P, L, a.K, lds);
+  else
+    tail_fine_post<T, T>(P, L, a.K, lds);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_shaped(TailL a) {
   if (a.skip && *a.skip) return;  // uniform over the grid
@@ -1823,8 +1980,9 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
   if (nprobs <= 0) return hipSuccess;
   static bool attr = false;
   if (!attr) {
-    const void* ks[4] = {(const void*)k_tail<float>, (const void*)k_tail<double>, (const void*)k_tail_shaped<float>,
-                         (const void*)k_tail_shaped<double>};
+    const void* ks[6] = {(const void*)k_tail<float>,        (const void*)k_tail<double>,
+                         (const void*)k_tail_shaped<float>, (const void*)k_tail_shaped<double>,
+                         (const void*)k_tail_full<float>,   (const void*)k_tail_full<double>};
     for (const void* kf : ks) {
       const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, kTailLdsBytes);
       if (e != hipSuccess) return e;
@@ -1834,7 +1992,11 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
   // the V-cycle from a zero iterate (the time step's own visit) takes the
   // prefetching kernel; other shapes and continued visits the shaped one
   const bool shaped = a.shape != 0 || !a.from_zero;
-  if (shaped && dbl)
+  if (a.full && dbl)
+    hipLaunchKernelGGL(k_tail_full<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  else if (a.full)
+    hipLaunchKernelGGL(k_tail_full<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+  else if (shaped && dbl)
     hipLaunchKernelGGL(k_tail_shaped<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
   else if (shaped)
     hipLaunchKernelGGL(k_tail_shaped<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);

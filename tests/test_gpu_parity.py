@@ -198,6 +198,36 @@ def _adaptive_run(lbm, p, prec, nsteps):
     return ne, F
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cyc", [P.CYCLE_V, P.CYCLE_W])
+def test_whole_problem_tail_in_adaptive_cycles(lbm, monkeypatch, prec, cyc):
+    """A problem whose finest level fits one workgroup (32 x 32) runs every
+    adaptive cycle after the stopping test as one launch: the finest level's
+    sweeps with the explicit force and the wall data of Dirichlet, traction
+    and symmetry walls, then the coarse levels.  Against the tile schedule
+    (BIOT_NO_FULL_TAIL=1) and, in FP64, the oracle replaying the cycle counts."""
+    n = 32
+    yy, xx = np.mgrid[0:n, 0:n] / n
+    body = np.stack([0.3 * np.sin(2 * np.pi * yy), 0.2 * np.cos(np.pi * xx)])
+    p = mixed_walls(n, n, seed=5).replace(ne_fixed=0, ne_tol=1e-7, ne_max=30, K=3, cycle=cyc, body_f=body)
+    ne, A = _adaptive_run(lbm, p, prec, 5)
+    monkeypatch.setenv("BIOT_NO_FULL_TAIL", "1")
+    ne_t, B = _adaptive_run(lbm, p, prec, 5)
+    d = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+    _say("whole-problem tail", prec, cyc, ne, ne_t, d)
+    if prec == "fp64":
+        assert ne == ne_t and max(d) < 1e-12, (ne, ne_t, d)
+        o = Oracle(p, threads=oracle_threads(), history=5)
+        o.set_ne_schedule(np.array(ne, dtype=np.int32))
+        o.step(5)
+        C = o.fields()
+        e = (rel(A["eta"], C["eta"]), rel(A["p"], C["p"]), rel(A["sigma"], C["sigma"]))
+        _say("  vs oracle", e)
+        assert max(e) < STEP_TOL, e
+    else:
+        assert max(d) < 1e-4, d
+
+
 def test_adaptive_cycles_shifted_and_large(lbm):
     """The adaptive schedule where the finest level of 512^2 runs single
     applications after the measuring sweep and the coarser depths fused
