@@ -678,6 +678,7 @@ struct Engine {
   // measuring sweep, norms, stopping test and a later V-cycle, AD_END: flow
   // step and counter, AD_UNITS: several units)
   std::vector<Op> ad_ops[5];
+  bool ad_loop = false;  // AD_FIRST runs every cycle of a step (whole-problem tail)
   hipGraphExec_t ad_graph[5] = {};
   bool ad_valid = false;
   bool xcd_order = true;
@@ -1233,10 +1234,17 @@ bp_status build_adaptive(Engine& E) {
     o.count = 1;
     return o;
   };
-  if (full)
-    E.ad_ops[AD_FIRST].push_back(full_tail(0, E.K));
-  else
+  E.ad_loop = full;
+  if (full) {
+    // every cycle of the step, with its stopping test, in one launch
+    Op o = full_tail(0, E.K);
+    o.tl.loop = 1;
+    o.tl.ne_max = P.ne_max;
+    o.tl.tol = P.ne_tol;
+    E.ad_ops[AD_FIRST].push_back(o);
+  } else {
     add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
+  }
   std::vector<Op>& u = E.ad_ops[AD_UNIT];
   if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
   add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);
@@ -1280,6 +1288,13 @@ bp_status adaptive_step(Engine& E) {
   int issued = 0;
   int* st = (int*)E.host_pin;
   for (;;) {
+    if (E.ad_loop) {  // the whole-problem tail ran every cycle and test
+      HIPCHK(hipMemcpyAsync(st, P.d.ad, 2 * sizeof(int), hipMemcpyDeviceToHost, E.stream));
+      HIPCHK(hipMemcpyAsync(E.host_pin + 1, P.d.ad_ratio, sizeof(double), hipMemcpyDeviceToHost, E.stream));
+      HIPCHK(hipStreamSynchronize(E.stream));
+      if (st[0] == 0) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
+      break;
+    }
     for (int k = 0; k + kAdUnits <= batch; k += kAdUnits) BPCHK(run_adaptive(E, AD_UNITS));
     for (int k = 0; k < batch % kAdUnits; ++k) BPCHK(run_adaptive(E, AD_UNIT));
     issued += batch;

@@ -122,6 +122,10 @@ struct TailL {
                    // is read from buffer fine_in (0 A, 1 B) and pre-smoothed fine_pre
                    // times; the cycle's result ends in A
   int fine_in, fine_pre;
+  int loop;        // full: all adaptive cycles of the step, each after the first
+                   // preceded by the measuring sweep and the stopping test
+  int ne_max;      // loop: at most this many cycles
+  double tol;      // loop: stop when ||g - S(g)|| <= tol ||g||
 };
 // deepest top level a cycle-shaped tail handles (levels 1..kTailMaxLevel)
 constexpr int kTailMaxLevel = 15;

@@ -1807,11 +1807,16 @@ __device__ __forceinline__ void tail_run_shaped(const ProbD& P, int lt, int K, i
 // post-collision populations) to the pulled values; R = 0 there.
 
 // one application of S on the finest level held by the workgroup (one cell
-// per thread): as tail_relax with the force (Fx, Fy) and wall terms `add`
+// per thread): as tail_relax with the force (Fx, Fy) and wall terms `add`.
+// mode 1: G <- (1 - gamma) G + gamma S(G); 0: G <- G - S(G); 3 (the
+// measuring sweep): G <- (1 - gamma) G + gamma S(G) from the unscaled S(G),
+// adding ||G - S(G)||^2 and ||G||^2 of the cell to (mr, mg) in FP64
 template <typename T>
 __device__ __forceinline__ void tail_relax_fine(const ElConst<T>& k, int n, const TailTab (&tb)[1], T (&G)[1][8],
-                                                T Fx, T Fy, const T (&add)[8], T* sD, T* sG, bool blend) {
+                                                T Fx, T Fy, const T (&add)[8], T* sD, T* sG, int mode,
+                                                double* mr = nullptr, double* mg = nullptr) {
   const int c = threadIdx.x;
+  const bool blend = mode == 1;
   if (c < n) sD[c] = k.kD * el_ms(G[0]);
   __syncthreads();
   const T sc = blend ? k.gamma : T(1);
@@ -1843,7 +1848,14 @@ __device__ __forceinline__ void tail_relax_fine(const ElConst<T>& k, int n, cons
       const uint32_t code = (q & 1) ? hi16(tb[0].pl[q >> 1]) : lo16(tb[0].pl[q >> 1]);
       const T v = sG[code & 0x7fffu];
       const T gi = ((code & 0x8000u) ? -v : v) + sc * add[q];
-      G[0][q] = blend ? omg * G[0][q] + gi : G[0][q] - gi;
+      if (mode == 3) {
+        const double rho = double(G[0][q]) - double(gi);
+        *mr += rho * rho;
+        *mg += double(G[0][q]) * double(G[0][q]);
+        G[0][q] = omg * G[0][q] + k.gamma * gi;
+      } else {
+        G[0][q] = blend ? omg * G[0][q] + gi : G[0][q] - gi;
+      }
     }
   }
 }
@@ -1867,7 +1879,7 @@ __device__ __forceinline__ void tail_fine_terms(const ProbD& P, const LevelD& V,
 // pre-smoothing of the finest level L from buffer A or B (npre sweeps), the
 // iterate stored to A, the residual restricted into level L - 1's r
 template <typename T, typename T1>
-__device__ __forceinline__ void tail_fine_pre(const ProbD& P, int L, int npre, bool from_b, char* lds) {
+__device__ __forceinline__ void tail_fine_pre_g(const ProbD& P, int L, int npre, T (&G)[1][8], char* lds) {
   const int c = threadIdx.x;
   const LevelD& V = P.lv[L];
   const int nx = V.nx, ny = V.ny, n = nx * ny;
@@ -1875,13 +1887,12 @@ __device__ __forceinline__ void tail_fine_pre(const ProbD& P, int L, int npre, b
   T* sG = sD + n;
   const ElConst<T> k = tail_consts<T>(P);
   TailTab tb[1];
-  T G[1][8], add[8], Fx, Fy;
+  T add[8], Fx, Fy;
   tail_tab_load(P, L, c, tb);
-  tail_load1<T>(V, from_b ? V.gB : V.gA, c, G);
   tail_fine_terms<T>(P, V, c, Fx, Fy, add);
-  for (int s = 0; s < npre; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, true);
+  for (int s = 0; s < npre; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 1);
   tail_store1<T>(V, V.gA, c, G);
-  tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, false);
+  tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 0);
   __syncthreads();  // every pull has read sG
   if (c < n) {
 #pragma unroll
@@ -1914,6 +1925,14 @@ __device__ __forceinline__ void tail_fine_pre(const ProbD& P, int L, int npre, b
   __syncthreads();  // sG is reused by the coarser levels
 }
 
+template <typename T, typename T1>
+__device__ __forceinline__ void tail_fine_pre(const ProbD& P, int L, int npre, bool from_b, char* lds) {
+  const LevelD& V = P.lv[L];
+  T G[1][8];
+  tail_load1<T>(V, from_b ? V.gB : V.gA, threadIdx.x, G);
+  tail_fine_pre_g<T, T1>(P, L, npre, G, lds);
+}
+
 // post-smoothing of the finest level: its stored iterate plus the injected
 // coarse correction (in LDS, type TC), K sweeps, stored to A
 template <typename T, typename TC>
@@ -1937,8 +1956,74 @@ __device__ __forceinline__ void tail_fine_post(const ProbD& P, int L, int K, cha
   T* sD = (T*)lds;
   T* sG = sD + n;
   const ElConst<T> k = tail_consts<T>(P);
-  for (int s = 0; s < K; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, true);
+  for (int s = 0; s < K; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 1);
   tail_store1<T>(V, V.gA, c, G);
+}
+
+// the stopping test's state of the in-kernel adaptive loop, in LDS past the
+// levels' kTailLdsBytes
+struct TailFullState {
+  double ratio, rr, gg;
+  int stopped, count;
+};
+constexpr int kTailFullLdsBytes = kTailLdsBytes + 64;
+static_assert(sizeof(TailFullState) <= 64, "state fits its LDS slot");
+
+// one cycle of the whole problem: pre-smoothing from buffer A or B, the
+// coarse correction (one visit, or two for W (W, W) and F (F, V)), the
+// post-smoothing into A
+template <typename T>
+__device__ __forceinline__ void tail_full_cycle(const ProbD& P, const TailL& a, int npre, T (&G)[1][8], char* lds) {
+  const int L = P.L;
+  tail_fine_pre_g<T, double>(P, L, npre, G, lds);
+  const int visits = a.shape != 0 ? 2 : 1;
+  for (int v = 0; v < visits; ++v)  // one call site: one inlined copy of the recursion
+    tail_run_shaped<T, double>(P, L - 1, a.K, v == 0 ? a.shape : (a.shape == 1 ? 1 : 0), v == 0, lds);
+  if (L == 2)
+    tail_fine_post<T, double>(P, L, a.K, lds);
+  else
+    tail_fine_post<T, T>(P, L, a.K, lds);
+}
+
+// the measuring sweep of the adaptive schedule on the finest level: one
+// smoothing application of the iterate in A (its result, which the next
+// cycle continues from, left in G), with the FP64 squares ||g - S(g)||^2 and
+// ||g||^2 summed over the level in a fixed order (lanes, then waves)
+template <typename T>
+__device__ __forceinline__ void tail_measure(const ProbD& P, char* lds, T (&G)[1][8], double& rr, double& gg) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[P.L];
+  const int n = V.nx * V.ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[1];
+  T add[8], Fx, Fy;
+  tail_tab_load(P, P.L, c, tb);
+  tail_load1<T>(V, V.gA, c, G);
+  tail_fine_terms<T>(P, V, c, Fx, Fy, add);
+  double r = 0.0, g = 0.0;
+  tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 3, &r, &g);
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    r += __shfl_down(r, o, kWave);
+    g += __shfl_down(g, o, kWave);
+  }
+  __syncthreads();  // every pull has read sG: reuse the LDS for the sums
+  double* sw = (double*)lds;
+  const int w = c / kWave, nw = kTailThreads / kWave;
+  if (c % kWave == 0) {
+    sw[w] = r;
+    sw[nw + w] = g;
+  }
+  __syncthreads();
+  rr = 0.0;
+  gg = 0.0;
+  if (c == 0)
+    for (int v = 0; v < nw; ++v) {
+      rr += sw[v];
+      gg += sw[nw + v];
+    }
 }
 
 template <typename T>
@@ -1948,14 +2033,58 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_full(TailL a) {
   const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
   const int L = P.L;
   if (L < 2 || L - 1 > kTailMaxLevel || !P.addt) return;  // uniform; the host never asks for it
-  tail_fine_pre<T, double>(P, L, a.fine_pre, a.fine_in != 0, lds);
-  // the coarse correction: one visit, or two for W (W, W) and F (F, V)
-  tail_run_shaped<T, double>(P, L - 1, a.K, a.shape, true, lds);
-  if (a.shape != 0) tail_run_shaped<T, double>(P, L - 1, a.K, a.shape == 1 ? 1 : 0, false, lds);
-  if (L == 2)
-    tail_fine_post<T, double>(P, L, a.K, lds);
-  else
-    tail_fine_post<T, T>(P, L, a.K, lds);
+  // without the loop: one cycle from buffer fine_in with fine_pre
+  // pre-smoothing sweeps.  With it: all cycles of the step, the first from A
+  // unconditionally, each later one after the measuring sweep and the
+  // stopping test, which thread 0 takes in the FP64 steps of the tile
+  // schedule's test and hands to every thread; at most ne_max + 1 passes (the
+  // test stops at ne_max cycles).  The test's state sits in LDS past what the
+  // levels use (registers held across the cycles would spill) and is stored
+  // once at the end.  One call site of the cycle: one inlined copy.
+  TailFullState* st = (TailFullState*)(lds + kTailLdsBytes);
+  if (a.loop && threadIdx.x == 0) {
+    st->stopped = P.ad[0];
+    st->count = P.ad[1];
+    st->ratio = 0.0;
+    st->rr = 0.0;
+    st->gg = 0.0;
+  }
+  T G[1][8];
+  tail_load1<T>(P.lv[L], (!a.loop && a.fine_in) ? P.lv[L].gB : P.lv[L].gA, threadIdx.x, G);
+  int npre = a.loop ? a.K : a.fine_pre;
+  for (int pass = 0; pass <= a.ne_max; ++pass) {
+    tail_full_cycle<T>(P, a, npre, G, lds);
+    if (!a.loop) break;
+    double rr, gg;
+    tail_measure<T>(P, lds, G, rr, gg);
+    if (threadIdx.x == 0) {
+      st->rr = rr;
+      st->gg = gg;
+      if (!isfinite(rr) || !isfinite(gg)) P.flags[0] = 1;
+      if (!st->stopped) {
+        const double nr = sqrt(rr), ng = sqrt(gg);
+        st->ratio = ng > 0 ? nr / ng : 0.0;
+        if (!isfinite(nr) || !isfinite(ng))
+          st->stopped = 2;
+        else if (nr <= a.tol * ng || st->count >= a.ne_max)
+          st->stopped = 1;
+        else
+          st->count += 1;
+      }
+    }
+    __syncthreads();
+    const bool stop = st->stopped != 0;
+    __syncthreads();  // the LDS is reused by the next cycle
+    if (stop) break;
+    npre = a.K - 1;
+  }
+  if (a.loop && threadIdx.x == 0) {
+    P.norm2[0] = st->rr;
+    P.norm2[1] = st->gg;
+    P.ad_ratio[0] = st->ratio;
+    P.ad[1] = st->count;
+    P.ad[0] = st->stopped;
+  }
 }
 
 template <typename T>
@@ -1983,8 +2112,9 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
     const void* ks[6] = {(const void*)k_tail<float>,        (const void*)k_tail<double>,
                          (const void*)k_tail_shaped<float>, (const void*)k_tail_shaped<double>,
                          (const void*)k_tail_full<float>,   (const void*)k_tail_full<double>};
-    for (const void* kf : ks) {
-      const hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, kTailLdsBytes);
+    for (int i = 0; i < 6; ++i) {
+      const hipError_t e = hipFuncSetAttribute(ks[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               i >= 4 ? kTailFullLdsBytes : kTailLdsBytes);
       if (e != hipSuccess) return e;
     }
     attr = true;
@@ -1993,9 +2123,9 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
   // prefetching kernel; other shapes and continued visits the shaped one
   const bool shaped = a.shape != 0 || !a.from_zero;
   if (a.full && dbl)
-    hipLaunchKernelGGL(k_tail_full<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+    hipLaunchKernelGGL(k_tail_full<double>, dim3(nprobs), dim3(kTailThreads), kTailFullLdsBytes, s, a);
   else if (a.full)
-    hipLaunchKernelGGL(k_tail_full<float>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
+    hipLaunchKernelGGL(k_tail_full<float>, dim3(nprobs), dim3(kTailThreads), kTailFullLdsBytes, s, a);
   else if (shaped && dbl)
     hipLaunchKernelGGL(k_tail_shaped<double>, dim3(nprobs), dim3(kTailThreads), kTailLdsBytes, s, a);
   else if (shaped)
