@@ -2,6 +2,7 @@
 
 * Terzaghi consolidation series (Sec. 4.2): pressure p(t, x2) and surface
   subsidence S(t), written for the dimensional system (c0 kept explicit).
+* Steady flow through horizontal layers of different permeability.
 * Error norms of Sec. 4: discrete L2(D) and time-space L2(Q).
 """
 from __future__ import annotations
@@ -61,3 +62,15 @@ def rel_l2(a, b):
     nb = math.sqrt(float(np.sum(b * b)))
     d = math.sqrt(float(np.sum((a - b) ** 2)))
     return d / nb if nb > 0 else d
+
+
+def layered_steady_pressure(kappa_rows, h, p_bottom=1.0, p_top=0.0):
+    """Steady Darcy flow up a column of horizontal layers (kappa_rows[j] in
+    row j of height h), pressure given at the bottom and top faces: the flux
+    is the same through every layer, q = (p_bottom - p_top) / sum(h / kappa_j),
+    so p falls linearly inside each layer, by q h / kappa_j across layer j.
+    Returns p at the row centres."""
+    k = np.asarray(kappa_rows, dtype=np.float64)
+    res = h / k
+    q = (p_bottom - p_top) / res.sum()
+    return p_bottom - q * (np.concatenate([[0.0], np.cumsum(res)[:-1]]) + 0.5 * res)

@@ -19,6 +19,14 @@
  *   lattice diffusivity              k = kappa' dt / h^2, omega_f = 1/(3k + 1/2)
  *                                    (eq. pressure:rate).
  * Layout: array-of-structures, cell (x, y) at index y*nx + x.
+ *
+ * Pins: every function is checked by tests/test_oracle_pins.py and
+ * tests/test_oracle_cycles.py against closed forms, exact invariants,
+ * brute-force solves or values the paper states, except one, which is
+ * parity unpinned: the ghost values of the central-difference pressure
+ * gradient at non-periodic walls (the paper uses that gradient only on the
+ * periodic problem); there the oracle and the GPU path agree, and nothing
+ * independent fixes the value.
  */
 #include <math.h>
 #include <stdint.h>

@@ -152,6 +152,20 @@ def terzaghi(nx=8, ny=128, lam=1.0, mu=1.0, kappa=1.0, c0=0.1, alpha=1.0, load=1
                    ne_max=ne_max, name=f"terzaghi_{nx}x{ny}")
 
 
+def layered_column(n=32, nx=4, seed=3, kmin=0.1, kmax=1.0) -> Problem:
+    """Flow only (alpha = 0) up an x-periodic column of horizontal layers, one
+    log-uniform random permeability in [kmin, kmax] per row, pressure 1 at the
+    bottom face and 0 at the top; the elastic field stays zero (clamped
+    bottom, traction-free top).  kappa[:, 0] holds the layers."""
+    h = 1.0 / n
+    kr = 10 ** np.random.default_rng(seed).uniform(np.log10(kmin), np.log10(kmax), n)
+    bottom = Side.uniform(nx, EL_DIRICHLET, FLOW_DIRICHLET, (0.0, 0.0), 1.0)
+    top = Side.uniform(nx, EL_TRACTION, FLOW_DIRICHLET, (0.0, 0.0), 0.0)
+    base = terzaghi(nx=nx, ny=n)
+    return base.replace(sides=[base.sides[0], base.sides[1], bottom, top], kappa=kr[:, None] * np.ones((n, nx)),
+                        alpha=0.0, c0=1.0, dt=h * h, ne_fixed=1, K=1, levels=2, name=f"layered_{nx}x{n}")
+
+
 def terzaghi_paper(alpha: float, n: int, nx=None, **kw) -> Problem:
     """Terzaghi parameters of Sec. 4.2: E = 1, nu = 0.8 (plane stress),
     kappa = (lam + 2 mu + alpha^2)/(lam + 2 mu), load = alpha + (lam + 2 mu)/alpha,

@@ -404,6 +404,27 @@ def test_determinism_and_mirror_symmetry(lbm):
     assert np.abs(A["p"] - A["p"][:, ::-1]).max() < 1e-10 * np.abs(A["p"]).max()
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_shifted", 1e-4)])
+def test_layered_permeability_steady_state(lbm, prec, tol):
+    """Heterogeneous permeability: the GPU's steady flow through random
+    horizontal layers is the continuum's series-resistance solution (one flux
+    through every layer), to rounding in FP64.  In FP32 the fixed point of the
+    iteration carries about eps_32 / (1 - rho) of rounding, with 1 / (1 - rho)
+    ~ N^2 / (pi^2 k_min) ~ 1e3 for 32 rows and a lattice diffusivity of 0.1:
+    the bar is 1e-4 (measured 1e-5)."""
+    from oracle import analytic as An
+
+    p = P.layered_column()
+    s = lbm.Solver(p, prec)
+    s.step(16000)
+    F = s.fields()["p"]
+    s.close()
+    pc = An.layered_steady_pressure(p.kappa[:, 0], p.dx)
+    e = np.abs(F - pc[:, None]).max()
+    _say("layered steady state", prec, e)
+    assert e < tol
+
+
 def test_checkpoint_resume_is_bitwise(lbm):
     p = P.loaded_strip(n=64, alpha=0.8, ne_fixed=3)
     a = lbm.Solver(p, "fp64")

@@ -409,6 +409,20 @@ def test_terzaghi_steady_state_subsidence_is_exact():
     assert np.abs(F["eta"][1] + Sinf * y[:, None]).max() < 1e-9
 
 
+def test_heterogeneous_permeability_steady_state_is_series_resistance():
+    """Per-cell relaxation rates of the flow LBM (heterogeneous kappa): the
+    steady state through random layers is the continuum's piecewise-linear
+    pressure with one flux through all layers, to rounding.  A rate taken
+    from the wrong cell would move every interface by a cell."""
+    p = P.layered_column()
+    pc = A.layered_steady_pressure(p.kappa[:, 0], p.dx)
+    o = Oracle(p, threads=1)
+    o.step(16000)
+    F = o.fields()["p"]
+    assert np.abs(F - F[:, :1]).max() == 0.0          # x-periodic column: no x dependence
+    assert np.abs(F[:, 0] - pc).max() < 1e-10
+
+
 # ------------------------------------------------------------- multigrid
 def _brute_fixed_point(o, L, Ft):
     nx, ny = o.level_shape(L)
