@@ -22,11 +22,8 @@
  *
  * Pins: every function is checked by tests/test_oracle_pins.py and
  * tests/test_oracle_cycles.py against closed forms, exact invariants,
- * brute-force solves or values the paper states, except one, which is
- * parity unpinned: the ghost values of the central-difference pressure
- * gradient at non-periodic walls (the paper uses that gradient only on the
- * periodic problem); there the oracle and the GPU path agree, and nothing
- * independent fixes the value.
+ * brute-force solves, convergence to series solutions or values the paper
+ * states.
  */
 #include <math.h>
 #include <stdint.h>

@@ -364,8 +364,8 @@ def test_terzaghi_series_boundary_values():
     assert A.terzaghi_S(100.0, 0.2, 0.5, cf) == pytest.approx(0.5, rel=1e-12)
 
 
-def _terzaghi_errors(n, alpha, tf):
-    p = P.terzaghi_paper(alpha, n, ne_fixed=3, K=4)
+def _terzaghi_errors(n, alpha, tf, pressure_gradient=P.GRAD_MOMENTS):
+    p = P.terzaghi_paper(alpha, n, ne_fixed=3, K=4).replace(pressure_gradient=pressure_gradient)
     load = alpha + (p.lam + 2 * p.mu) / alpha
     c = A.terzaghi_constants(p.lam, p.mu, p.c0, alpha, p.kappa, load)
     y = (np.arange(p.ny) + 0.5) * p.dx
@@ -392,6 +392,17 @@ def test_terzaghi_first_order_convergence():
     rs = [math.log2(e[i][1] / e[i + 1][1]) for i in range(2)]
     assert all(0.9 < r < 1.3 for r in rp), (e, rp)
     assert rs[-1] > 0.75 and rs[-1] > rs[0], (e, rs)
+
+
+def test_terzaghi_central_gradient_converges_with_walls():
+    """The central-difference pressure gradient at walls (its ghost values,
+    R17): the Terzaghi column has a drained top and an impermeable bottom, and
+    with that gradient the pressure still converges to the series at first
+    order and the subsidence error falls with the grid."""
+    e = [_terzaghi_errors(n, 1.0, 0.05, P.GRAD_CENTRAL) for n in (8, 16, 32)]
+    rp = [math.log2(e[i][0] / e[i + 1][0]) for i in range(2)]
+    assert all(0.9 < r < 1.3 for r in rp), (e, rp)
+    assert e[0][1] > e[1][1] > e[2][1] and math.log2(e[1][1] / e[2][1]) > 0.5, e
 
 
 def test_terzaghi_steady_state_subsidence_is_exact():
