@@ -195,6 +195,35 @@ def fp64_alone_ms_per_step(p, steps=5):
     return 1e3 * ev / steps
 
 
+def terzaghi_series(t, y, lam, mu, c0, alpha, kappa, load):
+    """Terzaghi's consolidation column (Sec. 4.2) in closed form at time t > 0:
+    the pressure at heights y (bottom y = 0 impermeable, top y = 1 drained)
+    and the surface subsidence.  With m = lam + 2 mu and d = c0 m + alpha^2:
+    p0 = alpha load / d, consolidation coefficient c_f = m kappa / d,
+    S0 = load / (m + alpha^2 / c0), S_inf = load / m, a_k = (k + 1/2) pi;
+    p = p0 sum 2 (-1)^k / a_k exp(-a_k^2 c_f t) cos(a_k y) and
+    S = S_inf + (S0 - S_inf) sum 2 / a_k^2 exp(-a_k^2 c_f t)."""
+    import math
+    import numpy as np
+    m = lam + 2.0 * mu
+    d = c0 * m + alpha * alpha
+    p0, cf = alpha * load / d, m * kappa / d
+    S0, Sinf = load / (m + alpha * alpha / c0), load / m
+    y = np.asarray(y, dtype=np.float64)
+    pk = np.zeros_like(y)
+    sk = 0.0
+    k = 0
+    while True:
+        a = (k + 0.5) * math.pi
+        e = math.exp(-a * a * cf * t)
+        if e < 1e-300 or k > 100000:
+            break
+        pk += 2.0 * (-1) ** k / a * e * np.cos(a * y)
+        sk += 2.0 / (a * a) * e
+        k += 1
+    return p0 * pk, Sinf + (S0 - Sinf) * sk
+
+
 def terzaghi(steps=200, cycle=0):
     """Terzaghi 8 x 128 (3 levels), adaptive N_E to 1e-8, FP64: all 200 steps
     from t = 0 (cycle: shape of the multigrid cycle)."""
@@ -204,13 +233,21 @@ def terzaghi(steps=200, cycle=0):
     s = lbm.Solver(p, "fp64")
     t0 = time.perf_counter()
     s.step(steps)
-    s.fields()  # synchronises
+    F = s.fields()  # synchronises
     wall = time.perf_counter() - t0
     st = s.stats()
     s.close()
+    # against the closed form after the last step (the fields of step n are
+    # compared at time (n - 1) dt, as the oracle's Terzaghi pins do)
+    import numpy as np
+    y = (np.arange(p.ny) + 0.5) * p.dx
+    pa, Sa = terzaghi_series((steps - 1) * p.dt, y, p.lam, p.mu, p.c0, p.alpha, p.kappa, 1.0)
+    S = -float(np.mean(F["eta"][1][-1]))
     return {"steps": steps, "ms_per_step": round(1e3 * wall / steps, 4),
             "mlups": round(p.ncells * steps / wall / 1e6, 4), "mean_ne": round(st["total_cycles"] / steps, 2),
-            "levels": st["levels"]}
+            "levels": st["levels"],
+            "rel_l2_p_vs_series": float(np.sqrt(np.sum((F["p"] - pa[:, None]) ** 2) / np.sum(np.broadcast_to(pa[:, None], F["p"].shape) ** 2))),
+            "subsidence_rel_err_vs_series": abs(S - Sa) / abs(Sa)}
 
 
 def cycle_shapes(n=512, steps=5):

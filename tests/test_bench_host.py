@@ -50,3 +50,18 @@ def test_traffic_figure_needs_matching_kernel_sources(monkeypatch):
 def test_cpu_model_is_text_or_none():
     m = bench.cpu_model()
     assert m is None or (isinstance(m, str) and m)
+
+
+def test_terzaghi_series_matches_the_analytic_module():
+    """bench.py's own statement of the Terzaghi closed form (it may not import
+    the oracle outside its CPU-baseline leg) against oracle/analytic.py."""
+    import numpy as np
+    from oracle import analytic as A
+
+    lam, mu, c0, alpha, kappa, load = 1.0, 1.0, 0.1, 1.0, 1.0, 1.0
+    c = A.terzaghi_constants(lam, mu, c0, alpha, kappa, load)
+    y = (np.arange(128) + 0.5) / 128
+    for t in (1e-5, 3e-3, 0.2):
+        pa, Sa = bench.terzaghi_series(t, y, lam, mu, c0, alpha, kappa, load)
+        assert np.abs(pa - A.terzaghi_p(t, y, c["p0"], c["cf"])).max() < 1e-12
+        assert abs(Sa - A.terzaghi_S(t, c["S0"], c["Sinf"], c["cf"])) < 1e-12
