@@ -135,6 +135,20 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
            "sample": f"{n} coupled steps of the same {problem.nx}x{problem.ny} workload after 1 untimed step, "
                      f"FP64 C oracle, {threads} OpenMP threads"}
+    # the GPU path on the same steps of the same problem, against the oracle's
+    # fields (relative L2): the parity of the benchmarked configuration
+    try:
+        from paper_2409_11382_amd import lbm
+        F = o.fields()
+        out["gpu_vs_oracle"] = {"steps": n + 1}
+        for prec in ("fp64", "fp32_shifted"):
+            g = lbm.Solver(problem, prec)
+            g.step(n + 1)
+            G = g.fields()
+            g.close()
+            out["gpu_vs_oracle"][prec] = {k: _rel(G[k], F[k]) for k in ("eta", "p", "sigma")}
+    except Exception as e:  # the timing stands on its own
+        out["gpu_vs_oracle"] = {"error": str(e)}
     if threads > 1:  # and on one core, a smaller sample
         o1 = Oracle(problem, threads=1)
         o1.step(1)
