@@ -96,6 +96,30 @@ def test_adaptive_cycle_counts_follow_oracle(lbm, cyc):
     s.close()
 
 
+@pytest.mark.parametrize("cyc", SHAPES)
+def test_adaptive_shapes_on_the_tile_schedule(lbm, cyc):
+    """Adaptive W- and F-cycles on a problem too large for one workgroup
+    (124 x 68: the tile kernels on the finest depths, the shaped coarse tail
+    below, continued visits included), in FP64 and FP32 shifted storage,
+    against the oracle replaying the GPU's cycle counts."""
+    p = mixed_walls(124, 68, seed=3).replace(ne_fixed=0, ne_tol=1e-6, ne_max=20, K=3, cycle=cyc)
+    for prec, tol in (("fp64", STEP_TOL), ("fp32_shifted", 1e-5)):
+        s = lbm.Solver(p, prec)
+        ne = []
+        for _ in range(4):
+            s.step(1)
+            ne.append(s.stats()["last_ne"])
+        A = s.fields()
+        s.close()
+        o = Oracle(p, threads=oracle_threads(), history=4)
+        o.set_ne_schedule(np.array(ne, dtype=np.int32))
+        o.step(4)
+        B = o.fields()
+        e = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]), rel(A["sigma"], B["sigma"]))
+        _say("adaptive tile", cyc, prec, ne, e)
+        assert e[0] < tol and e[1] < tol, (prec, ne, e)
+
+
 def test_batch_of_w_cycles_equals_alone(lbm):
     """A batch of W-cycle problems of different sizes: each problem matches its
     lone solve (to rounding: the launch variants follow the cells a depth
