@@ -374,6 +374,8 @@ def main():
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--kernel-only", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
+    ap.add_argument("--only", choices=("batched", "terzaghi"),
+                    help="only that workload's measurement (for profiling runs); prints its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -389,6 +391,12 @@ def main():
     lbm.load_library()
     if args.kernel_only:
         kernel_only(args.kernel_iters, tune=not args.no_tune)
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": batched(args.batch_steps, 2, tune=not args.no_tune)}), flush=True)
+        return
+    if args.only == "terzaghi":
+        print(json.dumps({"terzaghi_8x128": terzaghi()}), flush=True)
         return
     prob = P.loaded_strip(n=args.n, alpha=1.0, ne_fixed=3, K=4)
     N = prob.ncells
