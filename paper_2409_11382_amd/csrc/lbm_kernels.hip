@@ -1650,28 +1650,16 @@ __device__ __forceinline__ void tail_hand_up(char* lds, int n, const TT (&G)[1][
   __syncthreads();
 }
 
-// pre-smoothing of level l >= 2 (K sweeps from zero or from buffer A), the
-// iterate stored to A, the residual restricted into level l - 1's r
+// the residual G of level l >= 2 (one cell per thread) summed over 2 x 2
+// blocks into level l - 1's right-hand side (type T, or T1 for level 1),
+// through LDS; the LDS may be reused after the return
 template <typename T, typename T1>
-__device__ __forceinline__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
+__device__ __forceinline__ void tail_restrict(const ProbD& P, int l, const T (&G)[1][8], char* lds) {
   const int c = threadIdx.x;
   const LevelD& V = P.lv[l];
   const int nx = V.nx, ny = V.ny, n = nx * ny;
-  T* sD = (T*)lds;
-  T* sG = sD + n;
-  const ElConst<T> k = tail_consts<T>(P);
-  TailTab tb[1];
-  T G[1][8], R[1][8];
-  tail_tab_load(P, l, c, tb);
-  tail_load1<T>(V, V.r, c, R);
-  if (zero)
-    tail_zero(G);
-  else
-    tail_load1<T>(V, V.gA, c, G);
-  for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
-  tail_store1<T>(V, V.gA, c, G);
-  tail_relax<T, 1>(k, n, tb, G, R, sD, sG, false);
-  __syncthreads();  // every pull has read sG
+  T* sG = (T*)lds + n;
+  __syncthreads();  // every pull of the residual sweep has read sG
   if (c < n) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
@@ -1701,6 +1689,30 @@ __device__ __forceinline__ void tail_pre(const ProbD& P, int l, int K, bool zero
     tail_store1<T1>(C, C.r, c, Rc);
   }
   __syncthreads();  // sG is reused by the next level
+}
+
+// pre-smoothing of level l >= 2 (K sweeps from zero or from buffer A), the
+// iterate stored to A, the residual restricted into level l - 1's r
+template <typename T, typename T1>
+__device__ __forceinline__ void tail_pre(const ProbD& P, int l, int K, bool zero, char* lds) {
+  const int c = threadIdx.x;
+  const LevelD& V = P.lv[l];
+  const int nx = V.nx, ny = V.ny, n = nx * ny;
+  T* sD = (T*)lds;
+  T* sG = sD + n;
+  const ElConst<T> k = tail_consts<T>(P);
+  TailTab tb[1];
+  T G[1][8], R[1][8];
+  tail_tab_load(P, l, c, tb);
+  tail_load1<T>(V, V.r, c, R);
+  if (zero)
+    tail_zero(G);
+  else
+    tail_load1<T>(V, V.gA, c, G);
+  for (int s = 0; s < K; ++s) tail_relax<T, 1>(k, n, tb, G, R, sD, sG, true);
+  tail_store1<T>(V, V.gA, c, G);
+  tail_relax<T, 1>(k, n, tb, G, R, sD, sG, false);
+  tail_restrict<T, T1>(P, l, G, lds);
 }
 
 // the coarsest level: 2K sweeps from zero or from buffer A, stored to A and
@@ -1893,36 +1905,7 @@ __device__ __forceinline__ void tail_fine_pre_g(const ProbD& P, int L, int npre,
   for (int s = 0; s < npre; ++s) tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 1);
   tail_store1<T>(V, V.gA, c, G);
   tail_relax_fine<T>(k, n, tb, G, Fx, Fy, add, sD, sG, 0);
-  __syncthreads();  // every pull has read sG
-  if (c < n) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sG[q * n + c] = G[0][q];
-  }
-  __syncthreads();
-  const LevelD& C = P.lv[L - 1];
-  const int cnx = nx / 2, cn = cnx * (ny / 2);
-  T sum[8];
-  if (c < cn) {
-    const int X = c % cnx, Y = c / cnx;
-    const int f0 = (2 * Y) * nx + 2 * X, f1 = f0 + nx;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sum[q] = (sG[q * n + f0] + sG[q * n + f0 + 1]) + (sG[q * n + f1] + sG[q * n + f1 + 1]);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) sum[q] = T(0);
-  }
-  if (L - 1 >= 2) {
-    T Rc[1][8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Rc[0][q] = sum[q];
-    tail_store1<T>(C, C.r, c, Rc);
-  } else {
-    T1 Rc[1][8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Rc[0][q] = T1(sum[q]);
-    tail_store1<T1>(C, C.r, c, Rc);
-  }
-  __syncthreads();  // sG is reused by the coarser levels
+  tail_restrict<T, T1>(P, L, G, lds);
 }
 
 template <typename T, typename T1>
