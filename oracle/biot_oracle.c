@@ -90,7 +90,15 @@ typedef struct {
     const double *el_value[4];    /* 2 per boundary cell */
     const double *p_value[4];     /* 1 per boundary cell */
     int32_t pressure_gradient;    /* 0: eq. pressure:gradient, 1: eq. pressure:gradient:alternative */
-    int32_t cycle;                /* 0: V-cycle (Algorithm 4), 1: W-cycle, 2: F-cycle */
+    int32_t cycle;                /* 0: V-cycle (Algorithm 4), 1: W-cycle, 2: F-cycle,
+                                     3: full multigrid (first cycle of a step), then V */
+    int32_t fstar_literal;        /* 1: self-dependence constant alpha^2/2 as printed in
+                                     eq. MG:selfdependence, for every r; 0: r alpha^2/2 */
+    int32_t coarse_sweeps;        /* smoothing steps on the coarsest level of a multigrid
+                                     hierarchy (levels >= 2); 0: the 2K of Algorithm 4 */
+    int32_t lag;                  /* Algorithm 1 only (one level, gamma = 1): the implicit
+                                     source uses the divergence of the previous pseudo-time
+                                     step (eq. source:implicit) instead of the current one */
 } or_problem;
 
 typedef struct {
@@ -127,6 +135,8 @@ typedef struct {
     const int *ne_sched; int ne_sched_len;
     int threads;
     long coarsest_visits;    /* coarsest-level solves so far (cycle-shape pins) */
+    double *Dlag;            /* Algorithm 1 with the lag: divergence of the previous
+                                pseudo-time step's iterate */
 } or_state;
 
 /* ---------------------------------------------------------------- helpers */
@@ -188,8 +198,9 @@ static void grad_central(const or_state *o, int nx, int ny, const double *q, dou
         }
 }
 
-/* self-dependence force F_*(g) = (r alpha^2 / 2) grad^c D(g) (eq. MG:selfdependence,
- * with the explicit/implicit split of eq. source:implicit) */
+/* self-dependence force F_*(g) = C* grad^c D(g) (eq. MG:selfdependence) with
+ * C* = r alpha^2 / 2, the implicit share of the centred source of eq.
+ * source:implicit, or the printed alpha^2 / 2 for every r (fstar_literal) */
 static void self_force(const or_state *o, const level_t *lv, const double *g, double *D, double *Fs)
 {
 #pragma omp parallel for schedule(static)
@@ -358,10 +369,36 @@ static void apply_S(const or_state *o, level_t *lv, const double *g, const doubl
     elastic_step(o, lv, lv->u, lv->F, lv->gs, out);
 }
 
+/* S(g) of Algorithm 1 read with the lag of eq. source:implicit: the implicit
+ * source, hence the self-force, takes the divergence of the previous
+ * pseudo-time step's iterate (kept in Dlag), which then becomes the
+ * divergence of g.  A time step starts with Dlag = D(g) (g(-1) = g(0)), where
+ * this equals apply_S bitwise. */
+static void apply_S_lagged(const or_state *o, level_t *lv, const double *g, const double *r, const double *Ft,
+                           double *out)
+{
+    int n = lv->n;
+    grad_central(o, lv->nx, lv->ny, o->Dlag, lv->F);
+    for (int c = 0; c < 2 * n; ++c) lv->F[c] *= o->cstar;
+    if (Ft) for (int c = 0; c < 2 * n; ++c) lv->F[c] += Ft[c];
+    for (int c = 0; c < 8 * n; ++c) lv->u[c] = g[c] - (r ? r[c] : 0.0);
+    elastic_step(o, lv, lv->u, lv->F, lv->gs, out);
+    for (int c = 0; c < n; ++c) o->Dlag[c] = divergence_of(o, g + 8 * c);
+}
+
+/* start of a lagged pseudo-time run: g(-1) = g(0) */
+static void lag_reset(const or_state *o, const level_t *lv, const double *g)
+{
+    for (int c = 0; c < lv->n; ++c) o->Dlag[c] = divergence_of(o, g + 8 * c);
+}
+
 /* one under-relaxed smoothing step, eq. MG:smoother */
 static void smooth(const or_state *o, level_t *lv, double *g, const double *r, const double *Ft)
 {
-    apply_S(o, lv, g, r, Ft, lv->S);
+    if (o->Dlag)
+        apply_S_lagged(o, lv, g, r, Ft, lv->S);
+    else
+        apply_S(o, lv, g, r, Ft, lv->S);
     for (int c = 0; c < 8 * lv->n; ++c) g[c] = (1.0 - o->gamma) * g[c] + o->gamma * lv->S[c];
 }
 
@@ -375,35 +412,103 @@ static void smooth(const or_state *o, level_t *lv, double *g, const double *r, c
  *      with the same coarse right-hand side;
  *   F: an F-visit, then a V-visit continuing from its result.
  * On the coarsest level (no recursion) every shape is the same 2K sweeps. */
-enum { CYC_V = 0, CYC_W = 1, CYC_F = 2 };
+enum { CYC_V = 0, CYC_W = 1, CYC_F = 2, CYC_FMG = 3 };
+
+/* residual g - g** of level l (eq. LBM:residual) summed over each 2x2 block
+ * into the right-hand side of level l - 1 (eq. MG:restriction) */
+static void restrict_residual(or_state *o, int l, const double *g, const double *r, const double *Ft)
+{
+    level_t *lv = &o->lv[l], *lc = &o->lv[l - 1];
+    apply_S(o, lv, g, r, Ft, lv->S);
+    memset(lc->r, 0, sizeof(double) * 8 * lc->n);
+    for (int y = 0; y < lv->ny; ++y)
+        for (int x = 0; x < lv->nx; ++x) {
+            int cf = y * lv->nx + x, cc = (y / 2) * lc->nx + (x / 2);
+            for (int q = 0; q < 8; ++q) lc->r[8 * cc + q] += g[8 * cf + q] - lv->S[8 * cf + q];
+        }
+}
+
+/* prolongation P = R^T: every fine cell of level l adds its coarse cell's value */
+static void prolong_add(or_state *o, int l, double *g)
+{
+    level_t *lv = &o->lv[l], *lc = &o->lv[l - 1];
+    for (int y = 0; y < lv->ny; ++y)
+        for (int x = 0; x < lv->nx; ++x) {
+            int cf = y * lv->nx + x, cc = (y / 2) * lc->nx + (x / 2);
+            for (int q = 0; q < 8; ++q) g[8 * cf + q] += lc->g[8 * cc + q];
+        }
+}
+
 static void elastic_mg(or_state *o, int l, double *g, const double *r, const double *Ft, int cyc)
 {
     level_t *lv = &o->lv[l];
+    if (l == 1 && o->L > 1 && o->pb.coarse_sweeps > 0) {
+        /* the coarsest level of a hierarchy with its own number of sweeps
+         * (Algorithm 4 without recursion is 2K of them) */
+        ++o->coarsest_visits;
+        for (int k = 0; k < o->pb.coarse_sweeps; ++k) smooth(o, lv, g, r, Ft);
+        return;
+    }
     if (l == 1) ++o->coarsest_visits;
     for (int k = 0; k < o->K; ++k) smooth(o, lv, g, r, Ft);
     if (l > 1) {
         level_t *lc = &o->lv[l - 1];
-        /* residual r = g - g** (eq. LBM:residual) and full-sum restriction
-         * (eq. MG:restriction) */
-        apply_S(o, lv, g, r, Ft, lv->S);
-        memset(lc->r, 0, sizeof(double) * 8 * lc->n);
-        for (int y = 0; y < lv->ny; ++y)
-            for (int x = 0; x < lv->nx; ++x) {
-                int cf = y * lv->nx + x, cc = (y / 2) * lc->nx + (x / 2);
-                for (int q = 0; q < 8; ++q) lc->r[8 * cc + q] += g[8 * cf + q] - lv->S[8 * cf + q];
-            }
+        restrict_residual(o, l, g, r, Ft);
         /* coarse correction from zero with the coarse residual, no explicit force */
         memset(lc->g, 0, sizeof(double) * 8 * lc->n);
         elastic_mg(o, l - 1, lc->g, lc->r, NULL, cyc);
         if (cyc != CYC_V) elastic_mg(o, l - 1, lc->g, lc->r, NULL, cyc == CYC_W ? CYC_W : CYC_V);
-        /* prolongation P = R^T: every fine cell takes its coarse cell's value */
-        for (int y = 0; y < lv->ny; ++y)
-            for (int x = 0; x < lv->nx; ++x) {
-                int cf = y * lv->nx + x, cc = (y / 2) * lc->nx + (x / 2);
-                for (int q = 0; q < 8; ++q) g[8 * cf + q] += lc->g[8 * cc + q];
-            }
+        prolong_add(o, l, g);
     }
     for (int k = 0; k < o->K; ++k) smooth(o, lv, g, r, Ft);
+}
+
+/* Full multigrid (the conclusion names it as future work without defining
+ * it), as the coarse-grid correction of a cycle.  fmg_solve computes the
+ * correction of level l from zero by nested iteration: the residual of the
+ * zero iterate (with the level's right-hand side) is restricted, the coarser
+ * correction is computed the same way, prolongated as the starting iterate,
+ * and one V-cycle on level l follows; on the coarsest level the correction
+ * is its smoothing sweeps from zero.  fmg_cycle is Algorithm 4 with that
+ * correction in place of the V-visit: K smoothing steps on the iterate (the
+ * warm start of the time step), its restricted residual, the correction by
+ * fmg_solve one level down, prolongation, K smoothing steps.  On one or two
+ * levels it is the V-cycle. */
+static void fmg_solve(or_state *o, int l, double *e, const double *r)
+{
+    if (l > 1) {
+        level_t *lc = &o->lv[l - 1];
+        restrict_residual(o, l, e, r, NULL);
+        memset(lc->g, 0, sizeof(double) * 8 * lc->n);
+        fmg_solve(o, l - 1, lc->g, lc->r);
+        prolong_add(o, l, e);
+    }
+    elastic_mg(o, l, e, r, NULL, CYC_V);
+}
+
+static void fmg_cycle(or_state *o, int l, double *g, const double *r, const double *Ft)
+{
+    level_t *lv = &o->lv[l];
+    if (l == 1) {
+        elastic_mg(o, l, g, r, Ft, CYC_V);
+        return;
+    }
+    level_t *lc = &o->lv[l - 1];
+    for (int k = 0; k < o->K; ++k) smooth(o, lv, g, r, Ft);
+    restrict_residual(o, l, g, r, Ft);
+    memset(lc->g, 0, sizeof(double) * 8 * lc->n);
+    fmg_solve(o, l - 1, lc->g, lc->r);
+    prolong_add(o, l, g);
+    for (int k = 0; k < o->K; ++k) smooth(o, lv, g, r, Ft);
+}
+
+/* cycle j (from 0) of a time step: full multigrid takes the first */
+static void step_cycle(or_state *o, int j)
+{
+    if (o->pb.cycle == CYC_FMG && j == 0)
+        fmg_cycle(o, o->L, o->g, NULL, o->Ft);
+    else
+        elastic_mg(o, o->L, o->g, NULL, o->Ft, o->pb.cycle == CYC_FMG ? CYC_V : o->pb.cycle);
 }
 
 /* ---------------------------------------------------------------- flow */
@@ -534,7 +639,7 @@ static void free_state(or_state *o)
     for (int s = 0; s < 4; ++s) { free(o->flow_type[s]); free(o->p_bc[s]); }
     free(o->om_f); free(o->f); free(o->g); free(o->D1); free(o->D2); free(o->Ft);
     free(o->fbody); free(o->src); free(o->eta); free(o->p); free(o->sig);
-    free(o->ne_hist); free(o->ratio_hist);
+    free(o->ne_hist); free(o->ratio_hist); free(o->Dlag);
     free(o);
 }
 
@@ -553,7 +658,8 @@ or_state *or_create(const or_problem *pb, int *err)
     if (pb->nx < 1 || pb->ny < 1 || pb->dx <= 0 || pb->dt <= 0 || pb->c0 <= 0 || pb->mu <= 0 ||
         pb->lambda + pb->mu <= 0 || pb->alpha < 0 || pb->alpha > 1 || pb->r < 0 || pb->r > 1 ||
         pb->gamma <= 0 || pb->gamma > 1 || pb->K < 1 || pb->pressure_gradient < 0 || pb->pressure_gradient > 1 ||
-        pb->cycle < 0 || pb->cycle > 2)
+        pb->cycle < 0 || pb->cycle > 3 || pb->fstar_literal < 0 || pb->fstar_literal > 1 ||
+        pb->coarse_sweeps < 0 || pb->coarse_sweeps % 2 != 0 || pb->lag < 0 || pb->lag > 1)
         return NULL;
     for (int s = 0; s < 4; ++s) if (pb->el_type[s] < 0 || pb->el_type[s] > 3) return NULL;
     if ((pb->el_type[LEFT] == EL_PERIODIC) != (pb->el_type[RIGHT] == EL_PERIODIC)) return NULL;
@@ -561,6 +667,7 @@ or_state *or_create(const or_problem *pb, int *err)
     int L = pb->levels > 0 ? pb->levels : or_default_levels(pb->nx, pb->ny);
     if (pb->nx % (1 << (L - 1)) || pb->ny % (1 << (L - 1))) return NULL;
     if (L > 1 && (pb->nx >> (L - 1) < 1 || pb->ny >> (L - 1) < 1)) return NULL;
+    if (pb->lag && (L != 1 || pb->ne_fixed < 1)) return NULL;   /* Algorithm 1 with fixed N_E only */
 
     or_state *o = (or_state *)calloc(1, sizeof(or_state));
     if (!o) { *err = OR_ERR_NOMEM; return NULL; }
@@ -576,7 +683,7 @@ or_state *or_create(const or_problem *pb, int *err)
     o->b_s = 3.0 * (o->lam + o->mu) / (3.0 * (o->lam + o->mu) + 1.0);
     o->b_d = 6.0 * o->mu / (6.0 * o->mu + 1.0);
     o->beta22 = 1.0 / (12.0 * (o->lam + o->mu) + 4.0);
-    o->cstar = o->r * o->alpha * o->alpha / 2.0;
+    o->cstar = (pb->fstar_literal ? 1.0 : o->r) * o->alpha * o->alpha / 2.0;
     int n = o->n;
     o->om_f = (double *)malloc(sizeof(double) * n);
     for (int c = 0; c < n; ++c) {
@@ -626,6 +733,7 @@ or_state *or_create(const or_problem *pb, int *err)
     o->sig = calloc(3 * n, sizeof(double));
     o->hist_cap = 0;
     o->threads = 1;
+    if (pb->lag) o->Dlag = calloc(n, sizeof(double));
     set_initial(o);
     *err = OR_OK;
     return o;
@@ -717,8 +825,9 @@ static int one_step(or_state *o)
     if (o->ne_sched && o->step < o->ne_sched_len) ne_fixed = o->ne_sched[o->step];
     int j = 0;
     double ratio = -1.0;
+    if (o->Dlag) lag_reset(o, lv, o->g);
     if (ne_fixed > 0) {
-        for (j = 0; j < ne_fixed; ++j) elastic_mg(o, o->L, o->g, NULL, o->Ft, o->pb.cycle);
+        for (j = 0; j < ne_fixed; ++j) step_cycle(o, j);
     } else {
         /* adaptive: before each cycle the residual of the current iterate is
          * compared with the iterate itself (stop when ||g - S(g)|| <= tol ||g||,
@@ -731,7 +840,7 @@ static int one_step(or_state *o)
             if (!isfinite(nr)) break;
             if (j >= 1 && nr <= o->pb.ne_tol * ng) break;
             if (j >= o->pb.ne_max) break;
-            elastic_mg(o, o->L, o->g, NULL, o->Ft, o->pb.cycle);
+            step_cycle(o, j);
             ++j;
         }
     }
@@ -868,8 +977,14 @@ int or_mg_cycle(or_state *o, int l, double *g, const double *r, const double *Ft
     double *ga = malloc(sizeof(double) * 8 * m), *ra = malloc(sizeof(double) * 8 * m);
     double *fa = malloc(sizeof(double) * 2 * m);
     planes_to_aos(g, ga, m, 8); planes_to_aos(r, ra, m, 8); planes_to_aos(Ft, fa, m, 2);
-    /* the recursion uses the level's own g buffer; work on a private copy */
-    elastic_mg(o, l, ga, r ? ra : NULL, Ft ? fa : NULL, o->pb.cycle);
+    /* the recursion uses the level's own g buffer; work on a private copy.
+     * Full multigrid runs its first cycle; the lagged Algorithm 1 starts as a
+     * time step does (g(-1) = g(0)). */
+    if (o->Dlag) lag_reset(o, lv, ga);
+    if (o->pb.cycle == CYC_FMG)
+        fmg_cycle(o, l, ga, r ? ra : NULL, Ft ? fa : NULL);
+    else
+        elastic_mg(o, l, ga, r ? ra : NULL, Ft ? fa : NULL, o->pb.cycle);
     aos_to_planes(ga, g, m, 8);
     free(ga); free(ra); free(fa);
     return OR_OK;

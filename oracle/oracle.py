@@ -42,7 +42,8 @@ class _Problem(C.Structure):
                 ("ne_tol", C.c_double), ("ne_max", C.c_int32),
                 ("el_type", C.c_int32 * 4), ("flow_type", C.POINTER(C.c_int8) * 4),
                 ("el_value", C.POINTER(C.c_double) * 4), ("p_value", C.POINTER(C.c_double) * 4),
-                ("pressure_gradient", C.c_int32), ("cycle", C.c_int32)]
+                ("pressure_gradient", C.c_int32), ("cycle", C.c_int32),
+                ("fstar_literal", C.c_int32), ("coarse_sweeps", C.c_int32), ("lag", C.c_int32)]
 
 
 _lib = None
@@ -114,6 +115,9 @@ class Oracle:
         pb.ne_fixed, pb.ne_tol, pb.ne_max = p.ne_fixed, p.ne_tol, p.ne_max
         pb.pressure_gradient = int(getattr(p, "pressure_gradient", 0))
         pb.cycle = int(getattr(p, "cycle", 0))
+        pb.fstar_literal = int(getattr(p, "fstar_literal", 0))
+        pb.coarse_sweeps = int(getattr(p, "coarse_sweeps", 0))
+        pb.lag = int(getattr(p, "lag", 0))
         for s in range(4):
             side = p.sides[s]
             fl = np.ascontiguousarray(side.flow, dtype=np.int8)

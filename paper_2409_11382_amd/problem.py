@@ -42,8 +42,9 @@ PREC_NAMES = {"fp64": PREC_FP64, "fp32": PREC_FP32,
 # (eq. pressure:gradient:alternative)
 GRAD_MOMENTS, GRAD_CENTRAL = 0, 1
 # multigrid cycle shape: the V-cycle of Algorithm 4; W- and F-cycles (named as
-# future work in the conclusion) in their textbook form
-CYCLE_V, CYCLE_W, CYCLE_F = 0, 1, 2
+# future work in the conclusion) in their textbook form; full multigrid (also
+# future work there) as the first cycle of every time step, V-cycles after it
+CYCLE_V, CYCLE_W, CYCLE_F, CYCLE_FMG = 0, 1, 2, 3
 
 
 @dataclasses.dataclass
@@ -92,7 +93,11 @@ class Problem:
     ne_max: int = 50
     name: str = ""
     pressure_gradient: int = 0         # GRAD_MOMENTS or GRAD_CENTRAL
-    cycle: int = 0                     # CYCLE_V, CYCLE_W or CYCLE_F
+    cycle: int = 0                     # CYCLE_V, CYCLE_W, CYCLE_F or CYCLE_FMG
+    fstar_literal: int = 0             # 1: self-dependence constant alpha^2/2 for every r
+    coarse_sweeps: int = 0             # smoothing steps on the coarsest level (0: 2K)
+    lag: int = 0                       # Algorithm 1 (one level): divergence of the previous
+                                       # pseudo-time step in the implicit source
 
     # ---- helpers ---------------------------------------------------------
     @property

@@ -152,4 +152,4 @@ def test_w_and_f_contract_faster_than_v_independently_of_the_grid():
 
 def test_unknown_cycle_shape_is_rejected():
     with pytest.raises(OracleError):
-        Oracle(P.loaded_strip(n=8).replace(cycle=3))
+        Oracle(P.loaded_strip(n=8).replace(cycle=4))
