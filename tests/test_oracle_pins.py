@@ -544,6 +544,194 @@ def test_adaptive_cycles_replay_bitwise():
     assert np.array_equal(Fa["eta"], Fb["eta"]) and np.array_equal(Fa["p"], Fb["p"])
 
 
+def test_adaptive_stopping_rule_by_its_definition():
+    """The adaptive N_E (Sec. 3.4 leaves the test open): before cycle j + 1,
+    j >= 1, the iterate g_j is accepted when ||g_j - S(g_j)|| <= tol ||g_j||,
+    with S one elastic application (eq. LBM:residual) and the norm over all
+    populations and cells.  Replayed here from the pinned single operations:
+    the count the oracle took is the first j >= 1 that passes, the ratio it
+    reports is that j's, and the state after the step is j cycles from the
+    warm start."""
+    p = P.terzaghi(nx=4, ny=32, ne_tol=3e-5, ne_max=12)
+    a = Oracle(p, threads=1, history=4)
+    a.step(3)
+    st = a.get_state()
+    Ft = a.explicit_force()
+    a.step(1)
+    ne, ratio = a.get_history()
+    j_took = int(ne[-1])
+    b = Oracle(p.replace(ne_fixed=1), threads=1)
+    L = b.levels
+    g = st["g"]
+    j, ratios = 0, []
+    while True:
+        rr = np.sqrt(np.sum((g - b.apply_elastic(L, g, None, Ft)) ** 2)) / np.sqrt(np.sum(g ** 2))
+        ratios.append(rr)
+        if (j >= 1 and rr <= p.ne_tol) or j >= p.ne_max:
+            break
+        g = b.mg_cycle(L, g, None, Ft)
+        j += 1
+    assert 2 <= j_took < p.ne_max, (ne, ratios)        # a decision inside the range
+    assert j == j_took and ratios[j] == pytest.approx(ratio[-1], rel=1e-12), (j, j_took, ratios, ratio)
+    assert ratios[j - 1] > p.ne_tol >= ratios[j]         # failed one cycle earlier
+    assert np.abs(a.get_state()["g"] - g).max() <= 1e-13 * np.abs(g).max()
+
+
+def test_adaptive_stopping_rule_edges():
+    """At least one cycle even when the warm start already passes (a huge
+    tolerance), and at most ne_max when it never does (a zero tolerance)."""
+    base = P.terzaghi(nx=4, ny=32, ne_max=7)
+    a = Oracle(base.replace(ne_tol=1e3), threads=1, history=3)
+    a.step(3)
+    assert list(a.get_history()[0]) == [1, 1, 1]
+    b = Oracle(base.replace(ne_tol=1e-300), threads=1, history=3)
+    b.step(3)
+    assert list(b.get_history()[0]) == [7, 7, 7]
+
+
+def test_elastic_initial_moments_with_a_body_force():
+    """Eqs. ICs, ICs:moments with a non-zero body force at t = 0 (p = 0, so
+    f_eff = f): before the first step the populations carry the moments
+    m10, m01 = -F/2, m12, m21 = -F/6 with F = h^2 c0 f (the force per
+    collision, lattice units) and zero stress moments, so the displacement
+    m10 + F/2 of eq. displacement is zero, as eta(0) = 0 requires."""
+    n = 8
+    p = P.loaded_strip(n=n, alpha=0.7, c0=0.3)
+    rng = np.random.default_rng(9)
+    body = rng.standard_normal((2, n, n))
+    o = Oracle(p.replace(body_f=body), threads=1)
+    g = o.get_state()["g"]
+    M = moment_matrix()
+    m = np.einsum("kq,qyx->kyx", M, g)
+    F = p.dx * p.dx * p.c0 * body
+    assert np.allclose(m[0], -F[0] / 2, rtol=0, atol=1e-15)
+    assert np.allclose(m[1], -F[1] / 2, rtol=0, atol=1e-15)
+    assert np.abs(m[2:5]).max() < 1e-15                 # m11, m_s, m_d
+    assert np.allclose(m[5], -F[0] / 6, rtol=0, atol=1e-15)
+    assert np.allclose(m[6], -F[1] / 6, rtol=0, atol=1e-15)
+    assert np.abs(m[7]).max() < 1e-15                   # m22
+    # the first step starts from these moments: with one V-cycle from them the
+    # displacement is the response to the load, not to a stale state
+    o.step(1)
+    fresh = Oracle(p.replace(body_f=body), threads=1)
+    fresh.step(1)
+    assert np.array_equal(o.fields()["eta"], fresh.fields()["eta"])
+
+
+def test_linear_pressure_with_nonuniform_dirichlet_data_is_exact():
+    """Flow only (alpha = 0), pressure Dirichlet on all four walls with the
+    data of a linear p = a + b x + c y at each boundary face centre: the
+    diffusion LBM's steady state is that linear field to rounding.  Every
+    axis link takes its face value; diagonal links take corner values (the
+    mean of two face values, exact for linear data), at the ends of a side by
+    linear extrapolation along it (eq. BC:pressure at the link midpoints)."""
+    nx, ny = 8, 6
+    h = 1.0 / nx
+    a, b, c = 0.3, 1.7, -0.9
+    xc, yc = (np.arange(nx) + 0.5) * h, (np.arange(ny) + 0.5) * h
+
+    def side(n, vals):
+        return P.Side(el=P.EL_SYMMETRY, flow=np.full(n, P.FLOW_DIRICHLET, np.int8),
+                      el_value=np.zeros((n, 2)), p_value=vals)
+
+    sides = [side(ny, a + c * yc), side(ny, a + b * nx * h + c * yc),
+             side(nx, a + b * xc), side(nx, a + b * xc + c * ny * h)]
+    p = P.Problem(nx=nx, ny=ny, dx=h, dt=h * h, lam=0.5, mu=0.5, c0=1.0, alpha=0.0, kappa=0.2,
+                  sides=sides, levels=1, K=1, ne_fixed=1)
+    o = Oracle(p, threads=1)
+    o.step(3000)
+    X, Y = np.meshgrid(xc, yc)
+    assert np.abs(o.fields()["p"] - (a + b * X + c * Y)).max() < 1e-13
+
+
+def _strip_growth(n, c0, steps):
+    p = P.loaded_strip(n=n, alpha=1.0, c0=c0, ne_fixed=3)
+    o = Oracle(p, threads=oracle_threads())
+    o.step(1)
+    first = np.abs(o.fields()["eta"]).max()
+    try:
+        o.step(steps - 1)
+    except OracleError:
+        return float("inf")
+    return np.abs(o.fields()["eta"]).max() / first
+
+
+def test_loaded_strip_needs_a_storage_coefficient_above_the_papers_coupling_range():
+    """R16: the strip family takes c0 = 1.  With the centred coupling and
+    MG(3,4) the coupled step is unstable once the coupling strength
+    alpha^2/(c0 (lam + 2 mu)) is far above the paper's experiments (at most
+    about 3.3): at c0 = 0.1 (about 9.1 for E = 1, nu = 0.3, alpha = 1) the
+    64^2 strip grows by orders of magnitude within 60 steps, while at c0 = 1
+    (about 0.9) it stays bounded over 100 steps."""
+    assert _strip_growth(64, 0.1, 60) > 1e4
+    assert _strip_growth(64, 1.0, 100) < 2.0
+
+
+def _terzaghi_column_errors(n, alpha, r, tf=0.05):
+    """Relative errors of p and of the subsidence against the series over
+    (0, tf], on an x-periodic column of 8 x n cells (the solution does not
+    depend on x; 8 columns keep a three-level hierarchy)."""
+    p = P.terzaghi_paper(alpha, n, nx=8, ne_fixed=3, K=4).replace(r=r)
+    load = alpha + (p.lam + 2 * p.mu) / alpha
+    c = A.terzaghi_constants(p.lam, p.mu, p.c0, alpha, p.kappa, load)
+    y = (np.arange(p.ny) + 0.5) * p.dx
+    acc = np.zeros(4)
+
+    def cb(k, o):
+        t = (k - 1) * p.dt
+        F = o.fields()
+        pa = A.terzaghi_p(t, y, c["p0"], c["cf"]) if t > 0 else np.full(p.ny, c["p0"])
+        Sa = A.terzaghi_S(t, c["S0"], c["Sinf"], c["cf"]) if t > 0 else c["S0"]
+        acc[0] += np.sum((F["p"] - pa[:, None]) ** 2)
+        acc[1] += np.sum(np.broadcast_to(pa[:, None], F["p"].shape) ** 2)
+        acc[2] += (-np.mean(F["eta"][1][-1]) - Sa) ** 2
+        acc[3] += Sa ** 2
+
+    run(p, int(round(tf / p.dt)), threads=1, every=1, callback=cb)
+    return math.sqrt(acc[0] / acc[1]), math.sqrt(acc[2] / acc[3])
+
+
+@pytest.mark.parametrize("alpha", [0.8, 0.9, 1.0])
+@pytest.mark.parametrize("r", [0.0, 0.5, 1.0])
+def test_terzaghi_first_order_for_every_coupling(alpha, r):
+    """Sec. 4.2: first-order convergence of the pressure for alpha in
+    {0.8, 0.9, 1.0} with the centred, explicit and implicit couplings
+    (MG(3,4)); the subsidence error falls at least at first order once the
+    grid resolves the early boundary layer (16 -> 32 rows)."""
+    e = [_terzaghi_column_errors(n, alpha, r) for n in (8, 16, 32)]
+    rp = [math.log2(e[i][0] / e[i + 1][0]) for i in range(2)]
+    rs = math.log2(e[1][1] / e[2][1])
+    assert all(0.85 < q < 1.35 for q in rp), (e, rp)
+    assert rs > 0.9, (e, rs)
+
+
+@pytest.mark.parametrize("r", [0.0, 0.5, 1.0])
+def test_terzaghi_instantaneous_response_after_eight_steps(r):
+    """Sec. 4.2: the solution matches from t = 1e-4 on, after 8 steps at
+    N_x = 128 (dt = dx^2/4).  By then the column carries the instantaneous
+    response of the loading: p = p0 = 1 in the interior (away from the
+    drained top) to 0.5% and the displacement eta = (0, -c0 p0 x2 / alpha)
+    (c0 = 1 with the paper's parameters) to 0.3%; the pressure matches the
+    series, boundary layer included, to 2%."""
+    alpha = 1.0
+    p = P.terzaghi_paper(alpha, 128, ne_fixed=3, K=4).replace(r=r)   # 128 x 128, 7 levels
+    load = alpha + (p.lam + 2 * p.mu) / alpha
+    c = A.terzaghi_constants(p.lam, p.mu, p.c0, alpha, p.kappa, load)
+    o = Oracle(p, threads=oracle_threads())
+    o.step(8)
+    F = o.fields()
+    t = 7 * p.dt                                # outputs of step n are at t_(n-1)
+    y = (np.arange(p.ny) + 0.5) * p.dx
+    interior = y < 0.75
+    assert np.abs(F["p"][interior] - c["p0"]).max() < 5e-3 * c["p0"]
+    eta2 = F["eta"][1][:, 0]
+    ref = -p.c0 * c["p0"] * y / alpha
+    assert np.linalg.norm(eta2 - ref) < 3e-3 * np.linalg.norm(ref)
+    assert np.abs(F["eta"][0]).max() < 1e-12 * np.abs(eta2).max()
+    pa = A.terzaghi_p(t, y, c["p0"], c["cf"])
+    assert np.linalg.norm(F["p"][:, 0] - pa) < 0.02 * np.linalg.norm(pa)
+
+
 def test_invalid_problems_are_rejected():
     base = P.loaded_strip(n=8)
     for bad in (dict(c0=0.0), dict(mu=-1.0), dict(alpha=1.5), dict(r=1.5), dict(gamma=1.5),
