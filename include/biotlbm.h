@@ -43,7 +43,10 @@ typedef enum {
   BP_ERR_ARG = -1,        /* invalid argument or parameter */
   BP_ERR_SHAPE = -2,      /* grid not compatible with the level hierarchy */
   BP_ERR_DEVICE = -3,     /* a HIP call failed */
-  BP_ERR_DIVERGED = -4,   /* non-finite populations or residual norms */
+  BP_ERR_DIVERGED = -4,   /* non-finite populations or residual norms, or (fixed N_E) the
+                             norm of the finest populations at the end of a step grown
+                             above 1e8 times the largest of its first 16 non-zero
+                             step-end values (the coupled scheme's instability, Sec. 4.1) */
   BP_ERR_WORKSPACE = -5,  /* workspace missing, misaligned or too small */
   BP_ERR_STATE = -6       /* solver unusable after an earlier error */
 } bp_status;
@@ -56,16 +59,24 @@ typedef enum {
 typedef enum { BP_FP64 = 0, BP_FP32 = 1, BP_FP32_SHIFTED = 2, BP_FP64_SHIFTED = 3 } bp_precision;
 
 /* shape of the multigrid cycle.  The paper gives the V-cycle (Algorithm 4:
- * one visit of the coarser level per cycle) and names W- and F-cycles as
- * future work (Sec. 5) without defining them; they take the textbook form:
- * W visits the coarser level twice, F makes an F-visit and then a V-visit,
- * the second visit continuing from the first's coarse iterate with the same
- * restricted right-hand side.  W- and F-cycles sweep every level with the
- * tile kernels (the one-workgroup coarse tail runs V-cycles), and a cycle on
- * L levels solves the coarsest 2^(L-1) (W) or L (F) times, so they pay off
- * only on shallow hierarchies.  A batch takes one shape; the server runs
- * V-cycles. */
-typedef enum { BP_CYCLE_V = 0, BP_CYCLE_W = 1, BP_CYCLE_F = 2 } bp_cycle;
+ * one visit of the coarser level per cycle) and names W- and F-cycles and
+ * full multigrid as future work (Sec. 5) without defining them; they take
+ * the textbook form.  W visits the coarser level twice, F makes an F-visit
+ * and then a V-visit, the second visit continuing from the first's coarse
+ * iterate with the same restricted right-hand side.  Large levels run on the
+ * tile kernels; the one-workgroup coarse tail runs the levels of at most 1024
+ * cells in any shape (W- and F-visits included), and a problem of at most
+ * 1024 cells runs whole cycles of any shape there.  A cycle on L levels
+ * solves the coarsest 2^(L-1) (W) or L (F) times, so they pay off only on
+ * shallow hierarchies.
+ * BP_CYCLE_FMG makes the first cycle of every time step a full-multigrid
+ * cycle on the correction of the warm start: the residual is restricted
+ * level by level (on coarse levels the residual of a zero iterate), the
+ * coarsest level is smoothed from zero, and every finer level takes the
+ * prolongated correction as its starting iterate for one V-cycle; later
+ * cycles of the step are V-cycles.  Its coarse levels run on the tile
+ * kernels.  A batch takes one shape; the server runs V-cycles. */
+typedef enum { BP_CYCLE_V = 0, BP_CYCLE_W = 1, BP_CYCLE_F = 2, BP_CYCLE_FMG = 3 } bp_cycle;
 
 /* flow boundary types (Sec. 3.6): periodic, pressure Dirichlet (halfway
  * anti-bounce-back, eq. BC:pressure), no flow (halfway bounce-back,
@@ -117,6 +128,20 @@ typedef struct {
                                add half the central gradient of the source */
   int32_t cycle;            /* bp_cycle: shape of the multigrid cycle (0 = the V-cycle of
                                Algorithm 4) */
+  int32_t fstar_literal;    /* self-dependence force f_* of eq. MG:selfdependence with the
+                               printed constant alpha^2/2 for every r (1), or with the
+                               implicit share r alpha^2/2 of the centred source of
+                               eq. source:implicit (0, default; equal for r = 1) */
+  int32_t coarse_sweeps;    /* smoothing steps on the coarsest level of a hierarchy
+                               (levels >= 2): 0 = the 2K of Algorithm 4, else an even
+                               number >= 2 (a batch needs one value and, if > 0, one
+                               hierarchy depth) */
+  int32_t lag;              /* Algorithm 1 with the lag of eq. source:implicit: the
+                               implicit source of pseudo-time step tau uses the
+                               divergence of step tau - dtau (a step starts with
+                               g(-1) = g(0)); needs levels = 1 and a fixed N_E
+                               (single solvers).  0: the current iterate, as the
+                               multigrid of Algorithm 4 evaluates f_* */
 } bp_problem;
 
 typedef struct bp_solver bp_solver;
@@ -127,7 +152,12 @@ typedef struct {
   int64_t total_cycles;     /* V-cycles since creation */
   double last_ratio;        /* last ||g - S(g)|| / ||g|| measured (adaptive mode; else -1) */
   int32_t levels;           /* multigrid levels in use */
-  int32_t diverged;         /* non-finite norm seen */
+  int32_t diverged;         /* non-finite norm or growth above 1e8 seen */
+  int32_t adaptive_steps;   /* adaptive mode: steps since creation */
+  int32_t steps_at_cap;     /* adaptive mode: steps that stopped at ne_max with the
+                               ratio still above ne_tol */
+  double max_ratio;         /* adaptive mode: largest ratio at the end of a step */
+  double mean_ratio;        /* adaptive mode: mean ratio at the end of a step */
 } bp_run_stats;
 
 /* Device bytes needed for problem p (host-only, pure). */
@@ -142,17 +172,26 @@ bp_status bp_create(const bp_problem *p, void *device_ws, size_t ws_bytes, void 
                     bp_solver **out);
 
 /* Advance nsteps coupled time steps (Algorithm 5).  Asynchronous on the
- * solver's stream in fixed-N_E mode (one captured HIP graph per step); the
- * adaptive mode synchronises once per V-cycle to read the residual ratio. */
+ * solver's stream in fixed-N_E mode (one captured HIP graph per step).  The
+ * adaptive mode (Sec. 3.4 leaves the pseudo-time stopping test open) runs
+ * the test on the device and enqueues the cycles in batches: it reads the
+ * stop flag once per batch (as many cycles as the previous step needed, then
+ * four at a time), or once per step where all of a step's cycles run in one
+ * whole-problem launch. */
 bp_status bp_step(bp_solver *s, int32_t nsteps);
 
-/* Replace body force and fluid source (host arrays, NULL = zero) for the next
- * steps; reinit != 0 also resets the state to the initial conditions. */
+/* Replace body force f and fluid source s of eqs. 1-4 (host arrays, NULL =
+ * zero) for the next steps; reinit != 0 also resets the state to the initial
+ * conditions of eqs. ICs, ICs:moments, which depend on the loads at t = 0. */
 bp_status bp_set_loads(bp_solver *s, const double *body_f, const double *source_s, int32_t reinit);
 
 /* Synchronise and copy the fields of the last completed step n (time n dt):
- * eta (2 x N), p (N), sigma (3 x N: 11, 12, 22) in dimensional units; any
- * pointer may be NULL.  Returns BP_ERR_DIVERGED if the state is not finite. */
+ * eta (2 x N, eq. displacement with the bared moments of eq. moments:bared),
+ * p (N, eq. pressure, before the flow update as Algorithm 5 computes it) and
+ * sigma (3 x N: 11, 12, 22, from the bared stress moments of eq.
+ * moments:stress) in dimensional units; any pointer may be NULL.  Returns
+ * BP_ERR_DIVERGED if the state is not finite or has grown above 1e8 times
+ * its first norm. */
 bp_status bp_get_fields(bp_solver *s, double *eta, double *p, double *sigma, int32_t *step);
 
 /* Checkpoint access in FP64 component planes: f (9 x N, D2Q9 order of Table 1),
@@ -182,6 +221,8 @@ bp_status bp_mg_cycle(bp_solver *s, int32_t level, double *g, const double *r, c
 bp_status bp_explicit_force(bp_solver *s, double *Ft);
 bp_status bp_level_shape(const bp_solver *s, int32_t level, int32_t *nx, int32_t *ny);
 
+/* Run statistics: time steps, the multigrid cycles N_E of Algorithm 5 per
+ * step, and the stopping test's ratios of the adaptive mode. */
 bp_status bp_stats(const bp_solver *s, bp_run_stats *st);
 
 /* ---- launch shapes and their autotuner.  The time-step schedule picks, per
@@ -246,6 +287,10 @@ bp_status bp_destroy(bp_solver *s);
  * restriction according to the cells it covers in all), and otherwise
  * agree to rounding (operations are fused differently in the variants). */
 typedef struct bp_batch bp_batch;
+/* A problem whose state diverges (BP_ERR_DIVERGED above) leaves the batch at
+ * the next check (every 8 steps of bp_batch_step, and at its end): its later
+ * steps are not run, its fields stay those of the check, bp_batch_get_fields
+ * returns BP_ERR_DIVERGED for it, and the others step on unchanged. */
 bp_status bp_batch_workspace_bytes(const bp_problem *probs, int32_t n, size_t *device_bytes);
 bp_status bp_batch_create(const bp_problem *probs, int32_t n, void *device_ws, size_t ws_bytes,
                           void *hip_stream, bp_batch **out);
@@ -274,6 +319,9 @@ bp_status bp_batch_destroy(bp_batch *b);
  * Requests must use the server's precision, K and fixed V-cycle count.
  * Calls on one server are not thread-safe; all device work runs on hip_stream.
  *
+ * A request whose state diverges (BP_ERR_DIVERGED) is failed and retired at
+ * the next check, every 8 steps, instead of running to its step count.
+ *
  * Request states (bp_server_poll): 0 queued, 1 running, 2 done, 3 failed. */
 typedef struct bp_server bp_server;
 bp_status bp_server_request_bytes(const bp_problem *p, size_t *device_bytes);
@@ -283,6 +331,8 @@ bp_status bp_server_submit(bp_server *s, const bp_problem *p, int32_t nsteps, in
 /* Run up to nsteps time steps (fewer if nothing is left to run); reports the
  * requests running and queued afterwards. */
 bp_status bp_server_advance(bp_server *s, int32_t nsteps, int32_t *n_active, int32_t *n_queued);
+/* state of a request and the time steps it has run (all of them once done;
+ * a failed request reports those it ran before it failed) */
 bp_status bp_server_poll(const bp_server *s, int64_t ticket, int32_t *state, int32_t *steps_done);
 /* Copy the fields of a finished request (eta 2 x N, p N, sigma 3 x N, any may
  * be NULL; fields at time nsteps dt, as bp_get_fields) and forget the ticket.

@@ -88,7 +88,12 @@ bp_status validate(const bp_problem* p) {
   if (p->K < 1) return fail(BP_ERR_ARG, "K must be >= 1");
   if (p->pressure_gradient != 0 && p->pressure_gradient != 1)
     return fail(BP_ERR_ARG, "pressure_gradient must be 0 (first moments) or 1 (central difference)");
-  if (p->cycle < BP_CYCLE_V || p->cycle > BP_CYCLE_F) return fail(BP_ERR_ARG, "cycle must be V (0), W (1) or F (2)");
+  if (p->cycle < BP_CYCLE_V || p->cycle > BP_CYCLE_FMG)
+    return fail(BP_ERR_ARG, "cycle must be V (0), W (1), F (2) or full multigrid (3)");
+  if (p->fstar_literal != 0 && p->fstar_literal != 1) return fail(BP_ERR_ARG, "fstar_literal must be 0 or 1");
+  if (p->coarse_sweeps < 0 || p->coarse_sweeps % 2 != 0)
+    return fail(BP_ERR_ARG, "coarse_sweeps must be 0 or an even number >= 2");
+  if (p->lag != 0 && p->lag != 1) return fail(BP_ERR_ARG, "lag must be 0 or 1");
   if (p->ne_fixed < 0) return fail(BP_ERR_ARG, "ne_fixed must be >= 0");
   if (p->ne_fixed == 0 && (!(p->ne_tol > 0) || p->ne_max < 1))
     return fail(BP_ERR_ARG, "adaptive mode needs ne_tol > 0 and ne_max >= 1");
@@ -110,6 +115,8 @@ bp_status validate(const bp_problem* p) {
   const int L = p->levels > 0 ? p->levels : default_levels(p->nx, p->ny);
   if (L > kMaxLevels || p->nx % (1 << (L - 1)) || p->ny % (1 << (L - 1)))
     return fail(BP_ERR_SHAPE, "nx and ny must be divisible by 2^(levels-1) (at most 16 levels)");
+  if (p->lag && (L != 1 || p->ne_fixed < 1))
+    return fail(BP_ERR_ARG, "the lagged self-force is Algorithm 1: one level and a fixed N_E");
   const int cx = p->nx >> (L - 1), cy = p->ny >> (L - 1);
   const bool perx = p->side[kLeft].el == BP_EL_PERIODIC, pery = p->side[kBottom].el == BP_EL_PERIODIC;
   if ((!perx && cx < 2) || (!pery && cy < 2))
@@ -139,6 +146,8 @@ struct Layout {
   std::vector<LevelLay> lv;  // 1..L
   size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
   size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_addt, off_elbc[4], off_ftype[4], off_flbc[4];
+  size_t off_dlag[2] = {SIZE_MAX, SIZE_MAX};
+  bool lag = false;
   int ntiles_fine = 0, ntiles_fine2 = 0;
   int tail_depth = 0;  // depth of the coarse tail's top level (0: no tail)
   size_t total = 0;
@@ -166,6 +175,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.fdbl = (p->prec == BP_FP64 || p->prec == BP_FP64_SHIFTED);
   lo.shift = (p->prec == BP_FP32_SHIFTED || p->prec == BP_FP64_SHIFTED);
   lo.cycle = p->cycle;
+  lo.lag = p->lag != 0;
   const size_t fs = lo.fdbl ? 8 : 4;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -219,12 +229,14 @@ void make_layout(const bp_problem* p, Layout& lo) {
     for (int alt = 0; alt < 2; ++alt)
       lo.ntiles_fine2 = std::max(lo.ntiles_fine2, sweepn_tiles(p->nx, p->ny, lo.fdbl, A, lo.shift, alt && A == 2));
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
-  lo.off_scal = take(64);
+  lo.off_scal = take(128);
+  if (lo.lag)
+    for (int k = 0; k < 2; ++k) lo.off_dlag[k] = take(lo.plane * fs);
   // a problem whose finest level fits the tail kernel, with the coarse tail
   // right below it, runs each adaptive cycle after the stopping test in one
   // workgroup (unshifted storage; BIOT_NO_FULL_TAIL=1 switches it off)
   lo.full_tail = !lo.shift && lo.L >= 2 && lo.tail_depth == 1 && lo.L - 1 <= kTailMaxLevel &&
-                 (int64_t)p->nx * p->ny <= (lo.fdbl ? kTailCellsF64 : kTailCellsF32);
+                 (int64_t)p->nx * p->ny <= (lo.fdbl ? kTailCellsF64 : kTailCellsF32) && lo.cycle != BP_CYCLE_FMG;
   if (const char* e = std::getenv("BIOT_NO_FULL_TAIL"))
     if (std::atoi(e) != 0) lo.full_tail = false;
   // gather tables of the coarse tail's levels (8 words per cell, level 1
@@ -265,7 +277,7 @@ size_t tile_entries_for(const Layout& lo) {
 }
 
 size_t engine_bytes(size_t nprobs, size_t tile_entries) {
-  return align_up(nprobs * sizeof(ProbD)) + align_up(tile_entries * sizeof(int2)) + align_up(nprobs * sizeof(int));
+  return align_up(nprobs * sizeof(ProbD)) + align_up(tile_entries * sizeof(int2)) + 2 * align_up(nprobs * sizeof(int));
 }
 
 // ------------------------------------------------------- boundary terms
@@ -373,9 +385,14 @@ struct Prob {
   int64_t total_cycles = 0;
   int last_ne = 0;
   double last_ratio = -1.0;
+  // adaptive statistics: steps, steps stopped at ne_max above the tolerance,
+  // largest and summed end-of-step ratios
+  int ad_steps = 0, ad_at_cap = 0;
+  double ad_max_ratio = 0.0, ad_sum_ratio = 0.0;
   bp_status status = BP_OK;
   int64_t user_id = -1;
-  bool fresh = true;  // initial conditions not yet written
+  bool fresh = true;     // initial conditions not yet written
+  bool evicted = false;  // diverged: no longer stepped (batch)
 };
 
 template <typename T>
@@ -468,7 +485,10 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.b_d = 6.0 * mu / (6.0 * mu + 1.0);
   d.beta22 = 1.0 / (12.0 * lm + 4.0);         // eq. moments:collision:22
   d.kD = -d.b_s / (2.0 * lm);                 // eq. LBM:divergence
-  d.cstar = p->r * p->alpha * p->alpha / 2.0; // implicit part of the centred source
+  // self-dependence constant of eq. MG:selfdependence: the implicit share r of
+  // the centred source (eq. source:implicit), or the printed value for every r
+  d.cstar = (p->fstar_literal ? 1.0 : p->r) * p->alpha * p->alpha / 2.0;
+  d.csweeps = p->coarse_sweeps > 0 ? p->coarse_sweeps : 2 * p->K;
   d.gamma = p->gamma;
   d.alpha = p->alpha;
   d.alpha_h = p->alpha / p->dx;
@@ -496,6 +516,8 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.flags = (int*)(base + lo.off_scal + 40);
   d.ad_ratio = (double*)(base + lo.off_scal + 16);
   d.ad = (int*)(base + lo.off_scal + 48);
+  d.gref = (double*)(base + lo.off_scal + 64);
+  for (int k = 0; k < 2; ++k) d.dlag[k] = lo.lag ? (void*)(base + lo.off_dlag[k]) : nullptr;
   d.ntiles_fine = lo.ntiles_fine;
   d.ttab = (uint32_t*)(base + lo.off_ttab);
   HIPCHK(launch_fill_zero(base, lo.total, st));
@@ -659,7 +681,10 @@ struct Engine {
   bool fdbl = true, shift = false;
   bool ref64 = false;  // shifted storage: some problem keeps FP64 references
   int K = 4, ne = 3, maxL = 1;
-  int cycle = BP_CYCLE_V;  // cycle shape of every problem
+  int cycle = BP_CYCLE_V;  // cycle shape of every problem (V for full multigrid's later cycles)
+  bool fmg = false;        // the first cycle of a step is a full-multigrid cycle
+  bool lag = false;        // Algorithm 1 with the lagged self-force (one problem, one level)
+  int csweeps = 0;         // coarsest-level sweeps of every problem on the tile path (0: 2K)
   std::vector<Prob*> probs;
   // engine area (device): descriptors, tile lists, problem ids
   char* area = nullptr;
@@ -667,6 +692,7 @@ struct Engine {
   ProbD* d_probs = nullptr;
   int2* d_tiles = nullptr;
   int* d_pids = nullptr;
+  int* d_div = nullptr;   // divergence flags by problem index (k_finalize)
   size_t tiles_cap = 0, probs_cap = 0;
   std::vector<DepthLists> depth;  // per depth
   int fine_off = 0, fine_cnt = 0; // depth-0 full-set tiles of every problem (flow)
@@ -820,6 +846,7 @@ bp_status engine_upload(Engine& E) {
   }
   if (!tiles.empty())
     HIPCHK(hipMemcpyAsync(E.d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, E.stream));
+  if (E.probs_cap) HIPCHK(launch_fill_zero(E.d_div, align_up(E.probs_cap * sizeof(int)), E.stream));
   HIPCHK(hipStreamSynchronize(E.stream));
   E.graph_valid = false;
   E.ad_valid = false;
@@ -899,8 +926,18 @@ int smoothing_launches(int count, bool quad, bool fuse) {
 // is swept by the tile kernels (inspection operations).  fuse: several
 // smoothing applications per launch (after a separate first sweep only where
 // the launch count keeps the iterate ending in A).
+// prolong_first: the first pre-smoothing application adds the coarser
+// depth's buffer A (the prolongated correction of full multigrid) to its
+// input.  A depth where every problem sits on its coarsest level takes the
+// problems' own number of coarsest sweeps (csweeps) in place of 2K, half as
+// pre- and half as post-smoothing so that the result ends in A.
+void add_fmg_solve(Engine& E, std::vector<Op>& ops, int d1);
+
+// fmg: the coarse-grid correction is computed by full multigrid from zero
+// (add_fmg_solve) in place of the V-, W- or F-visit.
 void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true,
-                bool fuse = false, int cyc = -1, bool from_zero = true) {
+                bool fuse = false, int cyc = -1, bool from_zero = true, bool prolong_first = false,
+                bool fmg = false) {
   if (d >= E.maxL) return;
   if (cyc < 0) cyc = E.cycle;
   const int full = tail ? 0 : 2, restr = full + 1;
@@ -927,26 +964,61 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
   }
   bool deeper = false;
   for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
+  const int nsm = (!deeper && d > 0 && E.csweeps > 0) ? E.csweeps / 2 : E.K;  // pre- and post-smoothing steps
   int sel = 0;
   bool restricted = false;
   if (first_done) {
     // the first pre-smoothing application (A -> B) was issued separately
-    sel = add_smoothing(E, ops, d, full, E.K - 1, 1, false, false, false, fuse_here, deeper && E.depth[d].fres,
+    sel = add_smoothing(E, ops, d, full, nsm - 1, 1, false, false, false, fuse_here, deeper && E.depth[d].fres,
                         &restricted);
   } else {
-    sel = add_smoothing(E, ops, d, full, E.K, 0, d > 0 && from_zero, false, false, fuse, deeper && E.depth[d].fres,
-                        &restricted);
+    sel = add_smoothing(E, ops, d, full, nsm, 0, d > 0 && from_zero, prolong_first, false, fuse,
+                        deeper && E.depth[d].fres, &restricted);
   }
   if (deeper) {
     if (!restricted) add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
     // the coarse correction: one V-visit; W: two W-visits, F: an F-visit then
     // a V-visit, the second continuing from the first's iterate (buffer A)
-    // with the same restricted right-hand side
-    add_vcycle(E, ops, d + 1, false, false, tail, fuse, cyc, true);
-    if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_W, false);
-    if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_V, false);
+    // with the same restricted right-hand side; or full multigrid
+    if (fmg) {
+      add_fmg_solve(E, ops, d + 1);
+    } else {
+      add_vcycle(E, ops, d + 1, false, false, tail, fuse, cyc, true);
+      if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_W, false);
+      if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_V, false);
+    }
   }
-  add_smoothing(E, ops, d, full, E.K, sel, false, true, partials_last && d == 0, fuse_here);
+  add_smoothing(E, ops, d, full, nsm, sel, false, true, partials_last && d == 0, fuse_here);
+}
+
+// Full multigrid (named as future work in the conclusion) for the coarse
+// correction of depths d1 and deeper, from zero, by nested iteration:
+// descending, the residual of a zero iterate with the depth's right-hand side
+// is restricted to the next depth; ascending from the deepest depth, each
+// depth runs one V-cycle from the prolongated correction of the depth below
+// (zero input plus prolongation; a problem's coarsest level takes its
+// sweeps from zero).  The result ends in buffer A of depth d1, where the
+// V-visit would leave it.  Every level runs on the tile kernels.
+void add_fmg_solve(Engine& E, std::vector<Op>& ops, int d1) {
+  for (int d = d1; d + 1 < E.maxL; ++d) add_sweeps(E, ops, d, 3, kRestrict, 2, 0, 0, 0);
+  for (int d = E.maxL - 1; d >= d1; --d) add_vcycle(E, ops, d, false, false, false, false, BP_CYCLE_V, true, true);
+}
+
+// Algorithm 1 with the lag of eq. source:implicit (one problem of one level,
+// fixed N_E): the step's 2K N_E applications as single launches, the first
+// taking its own divergence, every later one that of its predecessor's input
+void add_lagged_cycles(Engine& E, std::vector<Op>& ops) {
+  const int napps = 2 * E.K * E.ne;
+  int sel = 0;
+  for (int a = 0; a < napps; ++a) {
+    const size_t first = ops.size();
+    add_sweeps(E, ops, 0, 0, kSmooth, sel, 1 - sel, 0, a == napps - 1 ? 1 : 0);
+    for (size_t i = first; i < ops.size(); ++i) {
+      ops[i].sw.lag = a == 0 ? 1 : 2;
+      ops[i].sw.lag_rd = a == 0 ? 0 : (a - 1) % 2;
+    }
+    sel = 1 - sel;
+  }
 }
 
 Op cell_op(Engine& E, OpKind k) {
@@ -962,6 +1034,7 @@ Op prob_op(Engine& E, OpKind k) {
   o.kind = k;
   o.pl.probs = E.d_probs;
   o.pl.pids = E.d_pids;
+  o.pl.div = E.d_div;
   o.count = (int)E.probs.size();
   return o;
 }
@@ -997,12 +1070,18 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
     if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
     ops.push_back(cell_op(E, OP_FORCE));
   }
-  const int fusable = (E.shift && E.fuse && E.K >= 2) ? 2 * ((E.ne - 1) / 2) : 0;
+  const int fusable = (E.shift && E.fuse && E.K >= 2 && !E.lag) ? 2 * ((E.ne - 1) / 2) : 0;
   int cur = 0;  // reference buffer of the cycle
-  for (int j = 0; j < E.ne; ++j) {
+  if (E.lag) {
+    // Algorithm 1 with the lagged self-force: the displacement re-base of
+    // shifted storage leaves the divergence unchanged (it has no share in
+    // the stress moments), so the step's applications run back to back
+    add_lagged_cycles(E, ops);
+  }
+  for (int j = 0; j < E.ne && !E.lag; ++j) {
     if (E.shift && j > 0 && j > fusable) ops.push_back(cell_op(E, OP_REBASE_EL));
     const size_t first = ops.size();
-    add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse);
+    add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse, -1, true, false, j == 0 && E.fmg);
     for (size_t i = first; i < ops.size(); ++i)
       if (ops[i].kind == OP_SWEEP && ops[i].sw.depth == 0) ops[i].sw.eref_in = cur;
     if (j + 1 <= fusable) {
@@ -1023,7 +1102,7 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
     // the norms of the last post-smoothing launch (the flow step leaves them
     // alone), then the step counter, in one launch
     Op f = prob_op(E, OP_FINALIZE);
-    f.pl.fused = (E.fuse && E.K >= 2) ? 1 : 0;  // the last post-smoothing launch was multi-application
+    f.pl.fused = (E.fuse && E.K >= 2 && !E.lag) ? 1 : 0;  // the last post-smoothing launch was multi-application
     f.pl.advance = 1;
     ops.push_back(f);
   } else {
@@ -1141,11 +1220,13 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   E.d_probs = (ProbD*)area;
   E.d_tiles = (int2*)(area + align_up(probs_cap * sizeof(ProbD)));
   E.d_pids = (int*)((char*)E.d_tiles + align_up(tiles_cap * sizeof(int2)));
+  E.d_div = (int*)((char*)E.d_pids + align_up(probs_cap * sizeof(int)));
   E.fdbl = fdbl;
   E.shift = shift;
   E.K = K;
   E.ne = ne;
-  E.cycle = cycle;
+  E.fmg = cycle == BP_CYCLE_FMG;
+  E.cycle = E.fmg ? BP_CYCLE_V : cycle;
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
@@ -1245,6 +1326,8 @@ bp_status build_adaptive(Engine& E) {
     o.tl.ne_max = P.ne_max;
     o.tl.tol = P.ne_tol;
     E.ad_ops[AD_FIRST].push_back(o);
+  } else if (E.fmg) {
+    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse, -1, true, false, true);
   } else {
     add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
   }
@@ -1313,6 +1396,10 @@ bp_status adaptive_step(Engine& E) {
   P.last_ne = j;
   P.last_ratio = E.host_pin[1];
   P.total_cycles += j;
+  P.ad_steps += 1;
+  if (!(P.last_ratio <= P.ne_tol)) P.ad_at_cap += 1;  // stopped by ne_max
+  P.ad_max_ratio = std::max(P.ad_max_ratio, P.last_ratio);
+  P.ad_sum_ratio += P.last_ratio;
   BPCHK(run_adaptive(E, AD_END));
   P.step += 1;
   return BP_OK;
@@ -1467,6 +1554,23 @@ bp_status fields_of(Engine& E, Prob& P, double* eta, double* p, double* sigma, i
   return BP_OK;
 }
 
+// Problems whose finalize step flagged divergence since the last upload (one
+// small copy and a synchronisation).  Returns them in `out`.
+bp_status diverged_probs(Engine& E, std::vector<Prob*>& out) {
+  out.clear();
+  const size_t np = E.probs.size();
+  if (np == 0 || E.ne <= 0) return BP_OK;
+  std::vector<int> div(np, 0);
+  HIPCHK(hipMemcpyAsync(div.data(), E.d_div, np * sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  for (size_t i = 0; i < np; ++i)
+    if (div[i]) out.push_back(E.probs[i]);
+  return BP_OK;
+}
+
+// steps between divergence checks of batches and servers
+constexpr int kDivCheckSteps = 8;
+
 }  // namespace
 
 // ===================================================================== solver
@@ -1603,6 +1707,7 @@ struct bp_server {
   std::vector<SrvReq*> active;
   std::map<int64_t, std::unique_ptr<SrvReq>> reqs;
   bool dirty = false;
+  int steps_since_check = 0;
 };
 
 namespace {
@@ -1645,6 +1750,9 @@ bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void*
   s->ws = w;
   bp_status rc =
       engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed, p->cycle);
+  s->E.csweeps = p->coarse_sweeps;
+  s->E.lag = p->lag != 0;
+  if (s->E.lag) s->E.fuse = false;  // the lag runs single applications
   if (rc == BP_OK) rc = setup_problem(p, lo, w, st, s->P);
   if (rc == BP_OK) {
     s->E.probs = {&s->P};
@@ -1783,6 +1891,9 @@ bp_status bp_set_state(bp_solver* s, const double* f, const double* g, const dou
   }
   if (D1) BPCHK(upload_planes<double>(st, P.d.D[(n + 2) % 3], nx, ny, P.lo.pitch, P.lo.plane, D1, 1));
   if (D2) BPCHK(upload_planes<double>(st, P.d.D[(n + 1) % 3], nx, ny, P.lo.pitch, P.lo.plane, D2, 1));
+  // the growth test takes its reference from the restored state's steps
+  const double zero2[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(P.d.gref, zero2, sizeof(zero2), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   P.status = BP_OK;
   return BP_OK;
@@ -1834,7 +1945,16 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
   // tile kernels
   bool zero = !fine;
   for (size_t k = 0; k < (size_t)8 * v.nx * v.ny && zero; ++k) zero = g[k] == 0.0;
-  if (zero && d == P.lo.tail_depth) {
+  if (E.fmg) {
+    add_vcycle(E, ops, d, false, false, false, false, BP_CYCLE_V, false, false, true);
+  } else if (E.lag) {
+    // one cycle of Algorithm 1 (2K applications) as a time step starts it
+    const int ne = E.ne;
+    E.ne = 1;
+    add_lagged_cycles(E, ops);
+    E.ne = ne;
+    for (auto& o : ops) o.sw.partials = 0;
+  } else if (zero && d == P.lo.tail_depth) {
     add_vcycle(E, ops, d, false, false, true);
   } else {
     int sel = 0;
@@ -1851,6 +1971,15 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
     for (int k = 0; k < E.K; ++k) {
       add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);
       sel = 1 - sel;
+    }
+    if (level == 1 && P.L > 1 && E.csweeps > 0) {
+      // the coarsest level of the hierarchy: its own number of sweeps
+      ops.clear();
+      sel = 0;
+      for (int k = 0; k < E.csweeps; ++k) {
+        add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, 0, 0);
+        sel = 1 - sel;
+      }
     }
   }
   BPCHK(run_ops(E, ops));
@@ -1876,6 +2005,10 @@ bp_status bp_stats(const bp_solver* s, bp_run_stats* st) {
   st->total_cycles = s->P.total_cycles;
   st->last_ratio = s->P.last_ratio;
   st->levels = s->P.L;
+  st->adaptive_steps = s->P.ad_steps;
+  st->steps_at_cap = s->P.ad_at_cap;
+  st->max_ratio = s->P.ad_steps ? s->P.ad_max_ratio : -1.0;
+  st->mean_ratio = s->P.ad_steps ? s->P.ad_sum_ratio / s->P.ad_steps : -1.0;
   int flag = 0;
   if (hipMemcpy(&flag, s->P.d.flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(BP_ERR_DEVICE, "stats copy failed");
@@ -2002,6 +2135,15 @@ bp_status bp_batch_workspace_bytes(const bp_problem* probs, int32_t n, size_t* d
         probs[i].cycle != probs[0].cycle)
       return fail(BP_ERR_ARG, "a batch needs one precision, one K, one cycle shape and one fixed cycle count");
     if (probs[i].ne_fixed < 1) return fail(BP_ERR_ARG, "batched problems need a fixed V-cycle count");
+    if (probs[i].lag) return fail(BP_ERR_ARG, "the lagged self-force runs on single solvers");
+    if (probs[i].coarse_sweeps != probs[0].coarse_sweeps)
+      return fail(BP_ERR_ARG, "a batch needs one number of coarsest-level sweeps");
+    if (probs[i].coarse_sweeps > 0) {
+      Layout a, b;
+      make_layout(&probs[i], a);
+      make_layout(&probs[0], b);
+      if (a.L != b.L) return fail(BP_ERR_ARG, "coarsest-level sweeps in a batch need one hierarchy depth");
+    }
     Layout lo;
     make_layout(&probs[i], lo);
     total += lo.total;
@@ -2032,6 +2174,7 @@ bp_status bp_batch_create(const bp_problem* probs, int32_t n, void* device_ws, s
   for (int i = 0; i < n; ++i) off += los[i].total;
   bp_status rc = engine_init(b->E, w + off, need - off, (size_t)n, te, st, los[0].fdbl, los[0].shift, probs[0].K,
                              probs[0].ne_fixed, probs[0].cycle);
+  b->E.csweeps = probs[0].coarse_sweeps;
   off = 0;
   for (int i = 0; i < n && rc == BP_OK; ++i) {
     rc = setup_problem(&probs[i], los[i], w + off, st, b->P[i]);
@@ -2051,15 +2194,38 @@ bp_status bp_batch_create(const bp_problem* probs, int32_t n, void* device_ws, s
   return BP_OK;
 }
 
+// Steps every member that has not diverged; every kDivCheckSteps steps and at
+// the end a member that diverged leaves the engine's launches (its state and
+// fields stay as they are, its fields report BP_ERR_DIVERGED)
 bp_status bp_batch_step(bp_batch* b, int32_t nsteps) {
   if (!b) return fail(BP_ERR_ARG, "null batch");
-  for (int k = 0; k < nsteps; ++k) BPCHK(fixed_step(b->E));
+  if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
+  for (int k = 0; k < nsteps; ++k) {
+    if (!b->E.probs.empty()) BPCHK(fixed_step(b->E));
+    if ((k + 1) % kDivCheckSteps == 0 || k + 1 == nsteps) {
+      std::vector<Prob*> bad;
+      BPCHK(diverged_probs(b->E, bad));
+      if (bad.empty()) continue;
+      for (Prob* P : bad) {
+        P->status = BP_ERR_DIVERGED;
+        P->evicted = true;
+      }
+      b->E.probs.clear();
+      for (auto& P : b->P)
+        if (!P.evicted) b->E.probs.push_back(&P);
+      BPCHK(engine_upload(b->E));
+    }
+  }
   return BP_OK;
 }
 
 bp_status bp_batch_get_fields(bp_batch* b, int32_t i, double* eta, double* p, double* sigma, int32_t* step) {
   if (!b || i < 0 || i >= (int)b->P.size()) return fail(BP_ERR_ARG, "bad batch index");
-  BPCHK(extract_fields(b->E));
+  if (b->P[i].evicted) {
+    if (step) *step = b->P[i].step;
+    return fail(BP_ERR_DIVERGED, "the problem diverged and left the batch");
+  }
+  if (!b->E.probs.empty()) BPCHK(extract_fields(b->E));
   return fields_of(b->E, b->P[i], eta, p, sigma, step);
 }
 
@@ -2134,6 +2300,8 @@ bp_status bp_server_submit(bp_server* s, const bp_problem* p, int32_t nsteps, in
   if (p->prec != s->prec || p->K != s->K || p->ne_fixed != s->ne)
     return fail(BP_ERR_ARG, "a request must use the server's precision, K and fixed V-cycle count");
   if (p->cycle != BP_CYCLE_V) return fail(BP_ERR_ARG, "the server runs V-cycles");
+  if (p->coarse_sweeps != 0 || p->lag != 0)
+    return fail(BP_ERR_ARG, "the server runs the coarsest level's 2K sweeps and no lag");
   auto r = std::make_unique<SrvReq>();
   make_layout(p, r->lo);
   r->tiles = tile_entries_for(r->lo);
@@ -2203,6 +2371,20 @@ bp_status bp_server_advance(bp_server* s, int32_t nsteps, int32_t* n_active, int
     BPCHK(server_sync_members(s));
     if (s->active.empty()) break;
     BPCHK(fixed_step(s->E));
+    // a request that diverged fails at the next check instead of running on
+    if (++s->steps_since_check >= kDivCheckSteps) {
+      s->steps_since_check = 0;
+      std::vector<Prob*> bad;
+      BPCHK(diverged_probs(s->E, bad));
+      for (Prob* P : bad)
+        for (SrvReq* r : std::vector<SrvReq*>(s->active))
+          if (&r->P == P) {
+            r->state = kReqFailed;
+            r->status = BP_ERR_DIVERGED;
+            r->error = "the request's state diverged";
+            server_retire(s, r);
+          }
+    }
     std::vector<SrvReq*> done;
     for (SrvReq* r : s->active)
       if (r->P.step >= r->nsteps) done.push_back(r);
@@ -2231,7 +2413,7 @@ bp_status bp_server_poll(const bp_server* s, int64_t ticket, int32_t* state, int
   if (it == s->reqs.end()) return fail(BP_ERR_ARG, "unknown ticket");
   const SrvReq& r = *it->second;
   if (state) *state = r.state;
-  if (steps_done) *steps_done = r.state == kReqQueued ? 0 : (r.state == kReqRunning ? r.P.step : r.nsteps);
+  if (steps_done) *steps_done = r.state == kReqQueued ? 0 : (r.state == kReqDone ? r.nsteps : r.P.step);
   return BP_OK;
 }
 

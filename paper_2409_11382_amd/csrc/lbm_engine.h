@@ -68,7 +68,17 @@ struct ProbD {
   uint32_t* ttab;             // coarse tail: per-cell gather tables of levels 1.. (8 words per cell)
   void* addt;                 // whole-problem tail: the finest level's wall terms, 8 planes
                               // in the population precision (or null)
+  int csweeps;                // smoothing steps on the coarsest level of the hierarchy (2K
+                              // unless set)
+  void* dlag[2];              // Algorithm 1 with the lag: divergence of the previous
+                              // pseudo-time step's iterate, two planes in the population
+                              // precision (or null)
+  double* gref;               // growth test: [0] the largest ||g||^2 of the finest level at
+                              // the end of the first kGrowthWindow steps where it is non-zero,
+                              // [1] how many of those steps have passed
 };
+// step-end norms that set the growth test's reference
+constexpr double kGrowthWindow = 16.0;
 
 struct SweepL {
   const ProbD* probs;
@@ -82,6 +92,11 @@ struct SweepL {
   int eref_in;    // shifted storage: the displacement reference is eref (0) or eref2 (1)
   int rebase_out; // re-base the output on its displacement and write the new
                   // reference to the other buffer (finest level, smoothing)
+  int lag;        // lagged self-force (one-level problems, finest level, single
+                  // applications): 0 none, 1 the step's first application (its own
+                  // divergence, stored to dlag[0]), 2 the divergence of dlag[lag_rd],
+                  // the input's stored to dlag[1 - lag_rd]
+  int lag_rd;
 };
 
 struct CellL {    // per-cell kernels over the finest level
@@ -99,6 +114,8 @@ struct ProbL {    // one block per problem
   int decide;     // finalize: then the adaptive stopping test (tol, ne_max)
   double tol;
   int ne_max;
+  int* div;       // finalize: per problem index, set to 1 when the problem's state
+                  // is non-finite or its norm grew above 1e8 times its first value
 };
 
 // Coarse "tail" of the multigrid recursion: one 1024-thread workgroup per

@@ -97,6 +97,11 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
   k.kD = T(P.kD);
   k.cstar = T(P.cstar);
   k.gamma = T(P.gamma);
+  // lagged self-force (Algorithm 1 read with eq. source:implicit): the
+  // divergence of the previous pseudo-time step comes from dlag[lag_rd]; the
+  // input's own goes to the other plane for the next application
+  const T* dlag_in = (MODE == kSmooth && a.lag == 2) ? (const T*)P.dlag[a.lag_rd] : nullptr;
+  T* dlag_out = (MODE == kSmooth && a.lag != 0) ? (T*)P.dlag[a.lag == 1 ? 0 : 1 - a.lag_rd] : nullptr;
 
   T G[NK][8], Rv[NK][8], Fx[NK], Fy[NK];
 
@@ -115,7 +120,10 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) G[kk][q] += T(ec[q * cplane + cidx]);
     }
-    sD[j][lane] = k.kD * el_ms(G[kk]);
+    if (dlag_in)
+      sD[j][lane] = ok ? dlag_in[idx] : T(0);
+    else
+      sD[j][lane] = k.kD * el_ms(G[kk]);
     const bool crow = j >= 1 && j < CR + 1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) Rv[kk][q] = (ok && crow && rr) ? rr[q * plane + idx] : T(0);
@@ -275,6 +283,7 @@ __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
       if (valid) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = omg * G[kk][q] + gam * gi[q];
+        if (dlag_out) dlag_out[oidx] = k.kD * el_ms(G[kk]);
       }
     } else if (MODE == kApply) {
       if (valid) {
@@ -1082,6 +1091,8 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
   if (te.y == 0 && threadIdx.x == 0) {
     *P.phase = 0;
     P.flags[0] = 0;
+    P.gref[0] = 0.0;
+    P.gref[1] = 0.0;
   }
   const CellPos c = cell_pos(V, te.y);
   if (!c.in) return;
@@ -1550,7 +1561,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
     tail_load1<T>(P.lv[2], P.lv[2].gA, c, Gn);
     tail_load1<T>(P.lv[2], P.lv[2].r, c, Rn);
   }
-  // ---- coarsest level: 2K smoothing sweeps from zero
+  // ---- coarsest level: its smoothing sweeps (2K unless set) from zero
   {
     const LevelD& V = P.lv[1];
     const int n = V.nx * V.ny;
@@ -1563,7 +1574,7 @@ __device__ __forceinline__ void tail_run(const ProbD& P, int lt, int K, char* ld
       tail_tab_load(P, 1, c, tb);
     if (kPrefetch && lt >= 2) tail_tab_load(P, 2, c, tn);
     tail_zero(G1);
-    for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G1, R1, sD, sG, true);
+    for (int s = 0; s < P.csweeps; ++s) tail_relax<T1, 1>(k, n, tb, G1, R1, sD, sG, true);
     tail_store1<T1>(V, V.gA, c, G1);
     __syncthreads();  // every pull has read sG
     if (c < n) {
@@ -1715,8 +1726,8 @@ __device__ __forceinline__ void tail_pre(const ProbD& P, int l, int K, bool zero
   tail_restrict<T, T1>(P, l, G, lds);
 }
 
-// the coarsest level: 2K sweeps from zero or from buffer A, stored to A and
-// handed up through LDS
+// the coarsest level: its sweeps (2K unless the problem sets another count)
+// from zero or from buffer A, stored to A and handed up through LDS
 template <typename T1>
 __device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, bool zero, char* lds) {
   const int c = threadIdx.x;
@@ -1733,7 +1744,7 @@ __device__ __forceinline__ void tail_coarsest(const ProbD& P, int K, bool zero, 
     tail_zero(G);
   else
     tail_load1<T1>(V, V.gA, c, G);
-  for (int s = 0; s < 2 * K; ++s) tail_relax<T1, 1>(k, n, tb, G, R, sD, sG, true);
+  for (int s = 0; s < P.csweeps; ++s) tail_relax<T1, 1>(k, n, tb, G, R, sD, sG, true);
   tail_store1<T1>(V, V.gA, c, G);
   tail_hand_up<T1>(lds, n, G);
 }
@@ -2148,7 +2159,22 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
   if (threadIdx.x == 0) {
     P.norm2[0] = sr[0];
     P.norm2[1] = sg[0];
+    // divergence: a non-finite norm, or (at the end of a fixed-cycle step)
+    // ||g|| grown above 1e8 times the largest of its first kGrowthWindow
+    // non-zero step-end values since the initial conditions.  The window
+    // keeps a first value at rounding level (loads that cancel at t = 0)
+    // from becoming the reference.
     if (!isfinite(sr[0]) || !isfinite(sg[0])) P.flags[0] = 1;
+    if (a.advance && isfinite(sg[0]) && sg[0] > 0.0) {
+      double* gr = P.gref;
+      if (gr[1] < kGrowthWindow) {
+        gr[0] = fmax(gr[0], sg[0]);
+        gr[1] += 1.0;
+      } else if (sg[0] > 1e16 * gr[0]) {
+        P.flags[0] = 1;
+      }
+    }
+    if (a.div && P.flags[0]) a.div[a.pids[blockIdx.x]] = 1;
     if (a.advance) *P.phase += 1;
     if (a.decide && !P.ad[0]) {
       // the host's stopping test of the adaptive schedule, in the same FP64

@@ -40,7 +40,8 @@ class _Problem(C.Structure):
                 ("r", C.c_double), ("levels", C.c_int32), ("K", C.c_int32), ("gamma", C.c_double),
                 ("ne_fixed", C.c_int32), ("ne_tol", C.c_double), ("ne_max", C.c_int32),
                 ("side", _Side * 4), ("prec", C.c_int32), ("pressure_gradient", C.c_int32),
-                ("cycle", C.c_int32)]
+                ("cycle", C.c_int32), ("fstar_literal", C.c_int32), ("coarse_sweeps", C.c_int32),
+                ("lag", C.c_int32)]
 
 
 class _Tuning(C.Structure):
@@ -63,7 +64,9 @@ def _tuning_struct(d):
 
 class _Stats(C.Structure):
     _fields_ = [("step", C.c_int32), ("last_ne", C.c_int32), ("total_cycles", C.c_int64),
-                ("last_ratio", C.c_double), ("levels", C.c_int32), ("diverged", C.c_int32)]
+                ("last_ratio", C.c_double), ("levels", C.c_int32), ("diverged", C.c_int32),
+                ("adaptive_steps", C.c_int32), ("steps_at_cap", C.c_int32),
+                ("max_ratio", C.c_double), ("mean_ratio", C.c_double)]
 
 
 _lib = None
@@ -183,6 +186,9 @@ def marshal_problem(p: Problem, prec="fp64"):
     pb.prec = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     pb.pressure_gradient = int(p.pressure_gradient)
     pb.cycle = int(p.cycle)
+    pb.fstar_literal = int(p.fstar_literal)
+    pb.coarse_sweeps = int(p.coarse_sweeps)
+    pb.lag = int(p.lag)
     return pb, keep
 
 

@@ -57,7 +57,10 @@ def test_degenerate_problems_are_rejected_on_the_host():
     base = P.loaded_strip(n=64)
     bad = [dict(nx=0), dict(ny=0), dict(dt=0.0), dict(dx=-1.0), dict(alpha=nan), dict(mu=nan),
            dict(gamma=1.5), dict(ne_fixed=0, ne_tol=0.0), dict(ne_fixed=0, ne_tol=1e-6, ne_max=0),
-           dict(pressure_gradient=2), dict(cycle=3), dict(cycle=-1),
+           dict(pressure_gradient=2), dict(cycle=4), dict(cycle=-1),
+           dict(fstar_literal=2), dict(coarse_sweeps=3), dict(coarse_sweeps=-2),
+           dict(lag=1),                                        # the lag is Algorithm 1: one level
+           dict(lag=1, levels=1, ne_fixed=0, ne_tol=1e-6),     # with a fixed N_E
            dict(levels=7),                                     # 64 / 2^6 = 1 cell on the coarsest level
            dict(nx=63, levels=2)]                              # odd width cannot coarsen
     for kw in bad:
@@ -79,7 +82,16 @@ def test_degenerate_problems_are_rejected_on_the_host():
     assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # one cycle shape per batch
     arr = (L._Problem * 2)(pw, pw)
     assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_OK
-    del ka, kb
+    pc, kc = L.marshal_problem(base.replace(coarse_sweeps=6), "fp32_shifted")
+    arr = (L._Problem * 2)(pa, pc)
+    assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # one coarsest sweep count
+    pd_, kd = L.marshal_problem(P.loaded_strip(n=32).replace(coarse_sweeps=6), "fp32_shifted")
+    arr = (L._Problem * 2)(pc, pd_)
+    assert lib.bp_batch_workspace_bytes(arr, 2, C.byref(n)) == L.BP_ERR_ARG   # and then one depth
+    pl, kl = L.marshal_problem(base.replace(levels=1, gamma=1.0, K=1, lag=1), "fp32_shifted")
+    arr = (L._Problem * 1)(pl)
+    assert lib.bp_batch_workspace_bytes(arr, 1, C.byref(n)) == L.BP_ERR_ARG   # the lag: single solvers
+    del ka, kb, kc, kd, kl
 
 
 def test_last_error_message():
