@@ -276,6 +276,23 @@ bp_status bp_device_copy(void *dst, const void *src, size_t bytes, void *hip_str
 
 bp_status bp_destroy(bp_solver *s);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bp_create on a workspace
+ * the library owns, a file-scope static device array of 64 MiB per device
+ * (held from the library's first use on that device until the process ends;
+ * a problem whose bp_workspace_bytes exceed it is refused with
+ * BP_ERR_WORKSPACE).  The solver then allocates nothing: no device or pinned
+ * host memory, and no captured graphs (its time steps launch their kernels
+ * directly, with the same kernels and results as bp_create's solver).  The
+ * caller still passes the problem's host arrays and reads the fields with
+ * bp_get_fields.  One such solver per device at a time: the array is shared
+ * by every call on that device and keeps the last solver's contents, so a
+ * second bp_create_static on the same device returns BP_ERR_STATE until
+ * bp_destroy releases the first; calls from several threads that would
+ * overlap on one device race and must be serialised by the caller.  The
+ * workspace is cleared where the solver needs zeros at creation. */
+bp_status bp_create_static(const bp_problem *p, void *hip_stream, bp_solver **out);
+
 /* ---- batches: many independent problems advanced together.  Every launch of
  * a time step covers the same multigrid depth of all problems (levels aligned
  * from the finest), so n problems cost about the launches of one.  Problems

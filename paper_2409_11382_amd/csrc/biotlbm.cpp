@@ -13,6 +13,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -720,6 +721,8 @@ struct Engine {
   int64_t qnarrow_max_cells = kQuadNarrowResCells;
   bool fuse_res = true;  // restriction fused into pre-smoothing on latency-bound depths
   double* host_pin = nullptr;
+  bool own_pin = false;        // host_pin from hipHostMalloc (else host_buf)
+  double host_buf[4] = {};     // staging of engines that allocate nothing
 };
 
 int tgroup(const Engine& E, const Prob& P, int depth) {
@@ -1210,8 +1213,10 @@ bp_status build_graph(Engine& E) {
   return BP_OK;
 }
 
+// no_alloc: the engine allocates nothing (no pinned staging buffer, no
+// captured graphs: kernels are launched directly)
 bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap, size_t tiles_cap, hipStream_t st,
-                      bool fdbl, bool shift, int K, int ne, int cycle = BP_CYCLE_V) {
+                      bool fdbl, bool shift, int K, int ne, int cycle = BP_CYCLE_V, bool no_alloc = false) {
   E.stream = st;
   E.area = area;
   E.area_bytes = area_bytes;
@@ -1234,8 +1239,14 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (const char* e = std::getenv("BIOT_QUAD_MAX_CELLS")) E.quad_max_cells = std::atoll(e);
   if (const char* e = std::getenv("BIOT_TALL_MAX_CELLS")) E.tall_max_cells = std::atoll(e);
   if (const char* e = std::getenv("BIOT_NO_FUSE_RES")) E.fuse_res = (std::atoi(e) == 0);
+  if (no_alloc) {
+    E.use_graph = false;
+    E.host_pin = E.host_buf;
+    return BP_OK;
+  }
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
+  E.own_pin = true;
   return BP_OK;
 }
 
@@ -1247,8 +1258,9 @@ void engine_release(Engine& E) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
-  if (E.host_pin) (void)hipHostFree(E.host_pin);
+  if (E.host_pin && E.own_pin) (void)hipHostFree(E.host_pin);
   E.host_pin = nullptr;
+  E.own_pin = false;
 }
 
 // one time step of every problem of the engine with a fixed number of
@@ -1571,6 +1583,44 @@ bp_status diverged_probs(Engine& E, std::vector<Prob*>& out) {
 // steps between divergence checks of batches and servers
 constexpr int kDivCheckSteps = 8;
 
+// ---- the static workspace of bp_create_static: one array per device, held
+// by the process until it ends.  In host code `scratch` names a host-side
+// stand-in, never a device address: the device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_busy[kMaxDevices] = {};
+
+// the current device's static workspace, reserved for one solver (released
+// by bp_destroy); its contents are whatever the last solver left
+bp_status scratch_acquire(int* dev_out, void** ptr_out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BP_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(BP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  if (g_scratch_busy[dev]) return fail(BP_ERR_STATE, "the device's static workspace is held by another solver");
+  g_scratch_busy[dev] = true;
+  *dev_out = dev;
+  *ptr_out = g_scratch_ptr[dev];
+  return BP_OK;
+}
+
+void scratch_release(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  g_scratch_busy[dev] = false;
+}
+
 }  // namespace
 
 // ===================================================================== solver
@@ -1578,6 +1628,7 @@ struct bp_solver {
   Engine E;
   Prob P;
   char* ws = nullptr;
+  int static_dev = -1;  // device whose static workspace the solver holds (bp_create_static)
 };
 
 struct bp_batch {
@@ -1734,22 +1785,19 @@ bp_status bp_workspace_bytes(const bp_problem* p, size_t* device_bytes) {
   return BP_OK;
 }
 
-bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void* hip_stream, bp_solver** out) {
-  if (!out) return fail(BP_ERR_ARG, "null output handle");
-  *out = nullptr;
-  BPCHK(validate(p));
-  Layout lo;
-  make_layout(p, lo);
+}  // extern "C"
+
+namespace {
+// bp_create on a given workspace; no_alloc: the engine allocates nothing
+bp_status create_solver(const bp_problem* p, const Layout& lo, char* w, void* hip_stream, bool no_alloc,
+                        bp_solver** out) {
   const size_t te = tile_entries_for(lo);
   const size_t need = lo.total + engine_bytes(1, te);
-  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0 || ws_bytes < need)
-    return fail(BP_ERR_WORKSPACE, "workspace missing, not 256-byte aligned or smaller than bp_workspace_bytes");
   bp_solver* s = new bp_solver();
   hipStream_t st = (hipStream_t)hip_stream;
-  char* w = (char*)device_ws;
   s->ws = w;
-  bp_status rc =
-      engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed, p->cycle);
+  bp_status rc = engine_init(s->E, w + lo.total, need - lo.total, 1, te, st, lo.fdbl, lo.shift, p->K, p->ne_fixed,
+                             p->cycle, no_alloc);
   s->E.csweeps = p->coarse_sweeps;
   s->E.lag = p->lag != 0;
   if (s->E.lag) s->E.fuse = false;  // the lag runs single applications
@@ -1767,10 +1815,48 @@ bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void*
   *out = s;
   return BP_OK;
 }
+}  // namespace
+
+extern "C" {
+
+bp_status bp_create(const bp_problem* p, void* device_ws, size_t ws_bytes, void* hip_stream, bp_solver** out) {
+  if (!out) return fail(BP_ERR_ARG, "null output handle");
+  *out = nullptr;
+  BPCHK(validate(p));
+  Layout lo;
+  make_layout(p, lo);
+  const size_t need = lo.total + engine_bytes(1, tile_entries_for(lo));
+  if (!device_ws || ((uintptr_t)device_ws % kAlign) != 0 || ws_bytes < need)
+    return fail(BP_ERR_WORKSPACE, "workspace missing, not 256-byte aligned or smaller than bp_workspace_bytes");
+  return create_solver(p, lo, (char*)device_ws, hip_stream, false, out);
+}
+
+bp_status bp_create_static(const bp_problem* p, void* hip_stream, bp_solver** out) {
+  if (!out) return fail(BP_ERR_ARG, "null output handle");
+  *out = nullptr;
+  BPCHK(validate(p));
+  Layout lo;
+  make_layout(p, lo);
+  const size_t need = lo.total + engine_bytes(1, tile_entries_for(lo));
+  if (need > kScratchBytes)
+    return fail(BP_ERR_WORKSPACE, "the problem needs " + std::to_string(need) + " bytes; the static workspace holds " +
+                                      std::to_string(kScratchBytes));
+  int dev = -1;
+  void* ptr = nullptr;
+  BPCHK(scratch_acquire(&dev, &ptr));
+  const bp_status rc = create_solver(p, lo, (char*)ptr, hip_stream, true, out);
+  if (rc != BP_OK) {
+    scratch_release(dev);
+    return rc;
+  }
+  (*out)->static_dev = dev;
+  return BP_OK;
+}
 
 bp_status bp_destroy(bp_solver* s) {
   if (!s) return BP_OK;
   engine_release(s->E);
+  if (s->static_dev >= 0) scratch_release(s->static_dev);
   delete s;
   return BP_OK;
 }

@@ -91,6 +91,7 @@ def load_library():
         for name, args in {
             "bp_workspace_bytes": [C.POINTER(_Problem), C.POINTER(C.c_size_t)],
             "bp_create": [C.POINTER(_Problem), vp, C.c_size_t, vp, C.POINTER(vp)],
+            "bp_create_static": [C.POINTER(_Problem), vp, C.POINTER(vp)],
             "bp_step": [vp, i32],
             "bp_set_loads": [vp, dp, dp, i32],
             "bp_get_fields": [vp, dp, dp, dp, C.POINTER(i32)],
@@ -203,7 +204,10 @@ def workspace_bytes(p: Problem, prec="fp64") -> int:
 class Solver:
     """One problem resident on a GPU.  Method names follow biotlbm.h."""
 
-    def __init__(self, p: Problem, prec="fp64", device="cuda:0", stream=None):
+    def __init__(self, p: Problem, prec="fp64", device="cuda:0", stream=None, static_workspace=False):
+        """static_workspace: bp_create_static (the library's static device
+        array as the workspace; nothing is allocated) instead of bp_create on
+        a workspace from PyTorch."""
         import torch
 
         lib = load_library()
@@ -214,14 +218,20 @@ class Solver:
         n = C.c_size_t(0)
         _check(lib.bp_workspace_bytes(C.byref(pb), C.byref(n)), "bp_workspace_bytes")
         self.ws_bytes = n.value
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         # a stream of its own (default priority): the library replays each time
         # step as one captured HIP graph, which the legacy null stream cannot hold
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-        self.ws.record_stream(self.stream)
         h = C.c_void_p(0)
-        _check(lib.bp_create(C.byref(pb), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
-                             C.c_void_p(self.stream.cuda_stream), C.byref(h)), "bp_create")
+        if static_workspace:
+            self.ws = None
+            with torch.cuda.device(self.device):
+                _check(lib.bp_create_static(C.byref(pb), C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+                       "bp_create_static")
+        else:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            self.ws.record_stream(self.stream)
+            _check(lib.bp_create(C.byref(pb), C.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)), "bp_create")
         del keep
         self._h = h
         self._lib = lib
