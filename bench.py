@@ -12,8 +12,10 @@ Beside it: the FP64 path on the same workload and its agreement with the FP32
 result, alpha = 1/2, the batched workload (256 loaded-strip problems of mixed
 size and parameters advanced together), the heterogeneous 2048 x 2048 strip,
 a served Poisson stream of solve requests (continuous batching; solves/s and
-p50/p99 latency), the roofline of the dominant kernel and the FP64 oracle on
-the host cores.
+p50/p99 latency), Terzaghi's column with adaptive cycle counts, the cycle
+shapes, plain pseudo-time stepping without multigrid (Algorithm 1), the
+roofline of the dominant kernel, a per-kernel breakdown of the step, and the
+FP64 oracle on the host cores.
 
 Prints one JSON line.  ``--kernel-only`` runs just the dominant kernel's timed
 launches and a plain device copy of known size (the command that the hardware
@@ -36,6 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # the kernel and the host code that orders its work lists (XCD-aware tile order)
 KERNEL_SOURCES = ("lbm_kernels.hip", "lbm_device.h", "lbm_engine.h", "biotlbm.cpp")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_fine_pair_sweep_fp32_shifted_512.txt")
+PMC_SUMMARY_2048 = os.path.join(ROOT, "profiles", "pmc_fine_pair_sweep_fp32_shifted_2048.txt")
+PMC_STEP_HET = os.path.join(ROOT, "profiles", "pmc_step_heterogeneous_2048_fp32_shifted.txt")
+PMC_STEP_BATCH = os.path.join(ROOT, "profiles", "pmc_step_batch_256_fp32_shifted.txt")
 COPY_BYTES = 256 << 20
 
 
@@ -52,14 +57,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or
-    None when the summary is missing or the kernel sources changed since."""
-    if not os.path.exists(PMC_SUMMARY):
+def measured_traffic(path=PMC_SUMMARY, key="hbm_bytes_per_launch"):
+    """HBM bytes (per launch of the dominant kernel, or per step) from a
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the
+    plain-copy calibration), or None when the summary is missing or the
+    kernel sources changed since."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(PMC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -67,9 +73,19 @@ def measured_traffic():
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_step_fraction(path, ms_per_step):
+    """The counters' HBM bytes of a whole step over the step's time, as a
+    fraction of 8 TB/s (None when the summary does not match the sources)."""
+    by = measured_traffic(path, "hbm_bytes_per_step")
+    if by is None:
+        return None
+    gbs = by / (ms_per_step * 1e-3) / 1e9
+    return {"hbm_bytes_per_step": by, "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def step_bytes_per_cell(p, fp64: bool, shifted: bool):
@@ -157,26 +173,93 @@ def cpu_baseline(problem, seconds_target=20.0, max_steps=40):
         o1.step(n1)
         dt1 = time.perf_counter() - t0
         out["one_core"] = {"value": round(problem.ncells * n1 / dt1 / 1e6, 4), "unit": "MLUPS", "steps": n1}
+    out["other_workloads"] = cpu_baseline_others(threads)
     return out
 
 
-def dominant_kernel(solver, iters):
-    """The finest-level smoothing launch of the step: two applications per
-    launch (k_tsweep2<float,float,fine,shift,2,no-restriction>), or four where
-    the tuning puts the finest depth on four-application launches.  Average
-    device time of `iters` back-to-back launches (one captured graph, HIP
-    events on the solver's stream) and its algorithmic bytes per launch: the
-    populations read and written once, the explicit force and the displacement
-    reference read once, 4 B each (80 B per cell)."""
+def cpu_baseline_others(threads):
+    """The oracle on bounded samples of the other workloads: Terzaghi 8 x 128
+    with adaptive cycles to 1e-8 (40 steps), one problem of each grid size of
+    the 256-problem batch (2 steps each), and one step of the heterogeneous
+    2048 x 2048 strip."""
+    from oracle.oracle import Oracle
+    from paper_2409_11382_amd import problem as P
+    res = {}
+
+    def timed(p, n):
+        o = Oracle(p, threads=threads)
+        t0 = time.perf_counter()
+        o.step(n)
+        return time.perf_counter() - t0
+
+    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50)
+    dt = timed(p, 40)
+    res["terzaghi_8x128"] = {"value": round(p.ncells * 40 / dt / 1e6, 5), "unit": "MLUPS", "steps": 40,
+                             "ms_per_step": round(1e3 * dt / 40, 3)}
+    probs = P.batch_problems(count=256, seed=1)
+    sample, seen = [], set()
+    for q in probs:
+        if q.nx not in seen:
+            seen.add(q.nx)
+            sample.append(q)
+    cells, secs = 0, 0.0
+    for q in sample:
+        secs += timed(q, 2)
+        cells += 2 * q.ncells
+    res["batch_sample"] = {"value": round(cells / secs / 1e6, 4), "unit": "MLUPS",
+                           "sample": "one problem of each grid size " + str(sorted(seen)) + ", 2 steps each"}
+    h = P.heterogeneous_strip(n=2048, ne_fixed=3, K=4)
+    dt = timed(h, 1)
+    res["heterogeneous_2048"] = {"value": round(h.ncells / dt / 1e6, 4), "unit": "MLUPS", "steps": 1,
+                                 "s_per_step": round(dt, 2)}
+    return res
+
+
+def dominant_kernel(solver, iters, label="float,float,fine,shift", bytes_per_app_cell=80):
+    """The finest-level smoothing launch of the step (the fine smoothing sweep
+    that carries most of a step's traffic): two applications per launch
+    (k_tsweep2<...,2,no-restriction>), or four where the tuning puts the
+    finest depth on four-application launches.  Average device time of
+    `iters` back-to-back launches (one captured graph, HIP events on the
+    solver's stream) and its algorithmic bytes per launch: per application and
+    cell the populations read and written, the explicit force and the
+    displacement reference read (8 + 8 + 2 + 2 values of 4 B in FP32 shifted
+    storage: 80 B), times the applications of the launch."""
     apps = 4 if solver.tuning()["quad_max_cells"] >= solver.p.ncells else 2
     us, nbytes = solver.time_kernel(4, iters)
     achieved = nbytes / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_tsweep2<float,float,fine,shift,{apps} applications> (finest-level smoothing "
+            "kernel": f"k_tsweep2<{label},{apps} applications> (finest-level smoothing "
                       f"{'pair' if apps == 2 else 'quad'})",
-            "avg_us": round(us, 3), "bytes_per_launch": nbytes, "bytes_per_cell": 80,
-            "applications_per_launch": apps, "launches_timed": iters}
+            "avg_us": round(us, 3), "bytes_per_launch": nbytes, "bytes_per_cell_application": bytes_per_app_cell,
+            "applications_per_launch": apps, "cells": solver.p.ncells, "launches_timed": iters}
+
+
+def kernel_breakdown(rows):
+    """bp_profile_step rows sorted by device time: time share, algorithmic MB
+    and the HBM fraction that those bytes over that time would reach."""
+    total = sum(r["us_per_step"] for r in rows) or 1.0
+    out = []
+    for r in sorted(rows, key=lambda r: -r["us_per_step"]):
+        gbs = r["bytes_per_step"] / (r["us_per_step"] * 1e-6) / 1e9 if r["us_per_step"] > 0 else 0.0
+        out.append({"kernel": r["name"], "depth": r["depth"], "launches": r["launches"],
+                    "us_per_step": round(r["us_per_step"], 2), "share": round(r["us_per_step"] / total, 4),
+                    "MB_per_step": round(r["bytes_per_step"] / 1e6, 3), "GBs": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return {"us_per_step": round(total, 2), "kernels": out}
+
+
+def fine_pair_share(breakdown):
+    """Share of the step's device time and algorithmic bytes in the finest
+    level's smoothing launches (depth 0, pairs or quads without the
+    restriction)."""
+    ks = breakdown["kernels"]
+    t = sum(k["us_per_step"] for k in ks) or 1.0
+    by = sum(k["MB_per_step"] for k in ks) or 1.0
+    sel = [k for k in ks if k["depth"] == 0 and k["kernel"].split()[0] in ("pair", "quad")]
+    return {"time": round(sum(k["us_per_step"] for k in sel) / t, 4),
+            "bytes": round(sum(k["MB_per_step"] for k in sel) / by, 4)}
 
 
 def batched(steps, warmup, count=256, tune=True):
@@ -190,11 +273,26 @@ def batched(steps, warmup, count=256, tune=True):
     tuning = b.autotune(steps=2) if tune else None
     wall, _ = time_steps(b, steps, warmup)
     per_step = wall / steps
+    brk = kernel_breakdown(b.profile_step(2))
     bytes_step = sum(step_bytes_per_cell(p, fp64=False, shifted=True) * p.ncells for p in probs)
     out = {"problems": count, "cells": cells, "steps_timed": steps, "tuning": tuning,
            "mlups": round(cells * steps / wall / 1e6, 2), "ms_per_step": round(1e3 * per_step, 4),
            "hbm_frac_byte_model": round(bytes_step / per_step / (HBM_PEAK_GBS * 1e9), 4),
-           "solves_per_s_300_steps": round(count / (300 * per_step), 3)}
+           "solves_per_s_300_steps": round(count / (300 * per_step), 3),
+           "hbm_frac_measured": measured_step_fraction(PMC_STEP_BATCH, 1e3 * per_step),
+           "step_breakdown": brk}
+    # the roofline of the batch's finest-level smoothing pairs (depth 0, all
+    # 256 problems in each launch), from the breakdown's per-launch events
+    pairs = [k for k in brk["kernels"] if k["depth"] == 0 and k["kernel"].startswith("pair ")]
+    if pairs:
+        k = pairs[0]
+        us = k["us_per_step"] / k["launches"]
+        nb = k["MB_per_step"] * 1e6 / k["launches"]
+        out["roofline"] = {"bound": "hbm", "achieved": round(nb / (us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": None, "kernel": "k_tsweep2 finest-level pair (" + k["kernel"] + ")",
+                           "avg_us": round(us, 3), "bytes_per_launch": nb,
+                           "share_of_step": fine_pair_share(brk)}
     b.close()
     return out
 
@@ -238,12 +336,15 @@ def terzaghi_series(t, y, lam, mu, c0, alpha, kappa, load):
     return p0 * pk, Sinf + (S0 - Sinf) * sk
 
 
-def terzaghi(steps=200, cycle=0):
+def terzaghi(steps=200, cycle=0, coarse_sweeps=0):
     """Terzaghi 8 x 128 (3 levels), adaptive N_E to 1e-8, FP64: all 200 steps
-    from t = 0 (cycle: shape of the multigrid cycle)."""
+    from t = 0 (cycle: shape of the multigrid cycle; coarse_sweeps: the
+    coarsest level's sweeps, 0 = the 2K of Algorithm 4).  Reports how many
+    steps stopped at N_E,max above the tolerance and the end-of-step ratios
+    ||g - S(g)|| / ||g|| actually reached."""
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
-    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50).replace(cycle=cycle)
+    p = P.terzaghi(ne_fixed=0, ne_tol=1e-8, ne_max=50).replace(cycle=cycle, coarse_sweeps=coarse_sweeps)
     s = lbm.Solver(p, "fp64")
     t0 = time.perf_counter()
     s.step(steps)
@@ -259,7 +360,8 @@ def terzaghi(steps=200, cycle=0):
     S = -float(np.mean(F["eta"][1][-1]))
     return {"steps": steps, "ms_per_step": round(1e3 * wall / steps, 4),
             "mlups": round(p.ncells * steps / wall / 1e6, 4), "mean_ne": round(st["total_cycles"] / steps, 2),
-            "levels": st["levels"],
+            "levels": st["levels"], "coarsest_sweeps": coarse_sweeps or 2 * p.K,
+            "steps_at_ne_max": st["steps_at_cap"], "max_ratio": st["max_ratio"], "mean_ratio": st["mean_ratio"],
             "rel_l2_p_vs_series": float(np.sqrt(np.sum((F["p"] - pa[:, None]) ** 2) / np.sum(np.broadcast_to(pa[:, None], F["p"].shape) ** 2))),
             "subsidence_rel_err_vs_series": abs(S - Sa) / abs(Sa)}
 
@@ -271,7 +373,7 @@ def cycle_shapes(n=512, steps=5):
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
     out = {}
-    for name, cyc in (("V", P.CYCLE_V), ("W", P.CYCLE_W), ("F", P.CYCLE_F)):
+    for name, cyc in (("V", P.CYCLE_V), ("W", P.CYCLE_W), ("F", P.CYCLE_F), ("FMG", P.CYCLE_FMG)):
         p = P.loaded_strip(n=n, alpha=1.0, ne_fixed=0, ne_tol=1e-6, ne_max=30).replace(cycle=cyc)
         s = lbm.Solver(p, "fp32_shifted")
         s.step(2)
@@ -329,20 +431,48 @@ def heterogeneous(steps, warmup, n=2048, tune=True):
                                                   / (wall / steps) / (HBM_PEAK_GBS * 1e9), 4),
                      "tuning": tuning}
         fields[prec] = s.fields()
+        if prec == "fp32_shifted":
+            res["roofline"] = dominant_kernel(s, 50)
+            res["roofline"]["traffic"] = measured_traffic(PMC_SUMMARY_2048)
+            res[prec]["hbm_frac_measured"] = measured_step_fraction(PMC_STEP_HET, 1e3 * wall / steps)
+            res["step_breakdown"] = kernel_breakdown(s.profile_step(3))
+            res["roofline"]["share_of_step"] = fine_pair_share(res["step_breakdown"])
         s.close()
     res["fp32_shifted_rel_l2_vs_gpu_fp64"] = {k: _rel(fields["fp32_shifted"][k], fields["fp64"][k])
                                              for k in ("eta", "p")}
     res["steps"] = steps + warmup
+    res["config"] = {"n": n, "levels": p.num_levels(), "K": p.K, "ne_fixed": p.ne_fixed,
+                     "pressure_gradient": "central difference of p (eq. pressure:gradient:alternative)",
+                     "kappa": "log-normal, sigma_log 1, correlation 32 cells, seed 0"}
     return res
 
 
-def kernel_only(iters, tune=True):
+def algorithm1(n=512, coeff=0.04, steps=2):
+    """Plain pseudo-time stepping without multigrid (Algorithm 1: one level,
+    gamma = 1) on the n x n strip in FP32 shifted storage, with the N_E =
+    coeff N_x^2 pseudo-time steps per time step at which Sec. 4.1's periodic
+    problem comes within a few per cent of the converged elastic error (the
+    oracle pins put 0.04 N_x^2 within 6%), against the benchmark's MG(3,4)."""
+    from paper_2409_11382_amd import lbm
+    from paper_2409_11382_amd import problem as P
+    half = max(1, int(round(coeff * n * n / 2)))
+    p = P.loaded_strip(n=n, alpha=1.0, ne_fixed=1, levels=1, K=half, gamma=1.0)
+    s = lbm.Solver(p, "fp32_shifted")
+    wall, _ = time_steps(s, steps, 1)
+    s.close()
+    return {"workload": f"loaded_strip_{n}x{n}", "pseudo_time_steps_per_step": 2 * half,
+            "ms_per_step": round(1e3 * wall / steps, 3), "mlups": round(p.ncells * steps / wall / 1e6, 4)}
+
+
+def kernel_only(iters, tune=True, n=512):
     """Dominant kernel launches and a plain copy of COPY_BYTES bytes, for the
-    kernel-trace and hardware-counter profiles."""
+    kernel-trace and hardware-counter profiles (n = 512: the benchmark's
+    strip; n = 2048: the heterogeneous strip)."""
     import torch
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
-    prob = P.loaded_strip(n=512, alpha=1.0, ne_fixed=3, K=4)
+    prob = (P.loaded_strip(n=512, alpha=1.0, ne_fixed=3, K=4) if n == 512
+            else P.heterogeneous_strip(n=n, ne_fixed=3, K=4))
     s = lbm.Solver(prob, "fp32_shifted")
     if tune:
         s.autotune(steps=5)  # the launch shapes the benchmark times
@@ -370,11 +500,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=30)
     ap.add_argument("--het-steps", type=int, default=100)
     ap.add_argument("--serve-rate", type=float, default=5.0)
-    ap.add_argument("--serve-count", type=int, default=24)
+    ap.add_argument("--serve-count", type=int, default=100)
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--kernel-only", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of the autotuner's")
-    ap.add_argument("--only", choices=("batched", "terzaghi"),
+    ap.add_argument("--only", choices=("batched", "terzaghi", "heterogeneous"),
                     help="only that workload's measurement (for profiling runs); prints its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -390,13 +520,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lbm.load_library()
     if args.kernel_only:
-        kernel_only(args.kernel_iters, tune=not args.no_tune)
+        kernel_only(args.kernel_iters, tune=not args.no_tune, n=args.n)
         return
     if args.only == "batched":
         print(json.dumps({"batched": batched(args.batch_steps, 2, tune=not args.no_tune)}), flush=True)
         return
     if args.only == "terzaghi":
         print(json.dumps({"terzaghi_8x128": terzaghi()}), flush=True)
+        return
+    if args.only == "heterogeneous":
+        print(json.dumps({"heterogeneous_2048": heterogeneous(args.het_steps, 2, tune=not args.no_tune)}),
+              flush=True)
         return
     prob = P.loaded_strip(n=args.n, alpha=1.0, ne_fixed=3, K=4)
     N = prob.ncells
@@ -412,6 +546,12 @@ def main():
     # the counters were taken on the pair launch
     roof["traffic"] = measured_traffic() if roof["applications_per_launch"] == 2 else None
     F32 = s32.fields()
+    # where the step's device time goes (10 more steps, each launch between
+    # HIP events); the fine smoothing sweep carries the largest share of the
+    # algorithmic bytes, the kernel with the largest share of time is named
+    brk = kernel_breakdown(s32.profile_step(10))
+    roof["share_of_step"] = fine_pair_share(brk)
+    roof["largest_by_time"] = dict(brk["kernels"][0])
     s32.close()
     b_step = step_bytes_per_cell(prob, fp64=False, shifted=True)
 
@@ -438,6 +578,7 @@ def main():
                           "frac": round(mlups32 * 1e6 * b_step / (HBM_PEAK_GBS * 1e9), 4)},
         "event_ms_per_step": round(1e3 * ev32 / args.steps, 5),
         "tuning": tuning,
+        "step_breakdown": brk,
     }
     s64 = lbm.Solver(prob, "fp64")
     tuning["fp64"] = s64.autotune(steps=5) if tune else s64.tuning()
@@ -470,17 +611,26 @@ def main():
         out["batched"] = batched(args.batch_steps, 2, tune=tune)
         from paper_2409_11382_amd import serve
         out["serving"] = serve.simulate(rate=args.serve_rate, count=args.serve_count, seed=2)
-        keys = ("rate_per_s", "requests", "solves_per_s", "p50_latency_s", "p99_latency_s", "mlups", "peak_active")
+        keys = ("rate_per_s", "requests", "completed", "solves_per_s", "p50_latency_s", "max_latency_s", "mlups",
+                "peak_active")
         out["serving_rate_sweep"] = [{k: v for k, v in serve.simulate(rate=r, count=12, seed=3).items() if k in keys}
                                      for r in (2.0, 10.0, 20.0, 50.0)]
         out["heterogeneous_2048"] = heterogeneous(args.het_steps, 2, tune=tune)
         out["terzaghi_8x128"] = terzaghi()
+        # the coarsest 2 x 32 level smoothed 512 times per visit reaches the tolerance
+        out["terzaghi_8x128"]["coarse_sweeps_512"] = terzaghi(coarse_sweeps=512)
         out["cycle_shapes"] = {"terzaghi_8x128_fp64": {"V": out["terzaghi_8x128"],
                                                        "W": terzaghi(cycle=P.CYCLE_W),
-                                                       "F": terzaghi(cycle=P.CYCLE_F)},
+                                                       "F": terzaghi(cycle=P.CYCLE_F),
+                                                       "FMG": terzaghi(cycle=P.CYCLE_FMG)},
                                "loaded_strip_%d_fp32_shifted" % args.n: cycle_shapes(args.n)}
-        out["speedups_over_fp64_alone"] = speedups_over_fp64_alone(out["batched"], args.serve_rate,
-                                                                   args.serve_count)
+        alg1 = algorithm1(args.n)
+        alg1["mg_ms_per_step"] = out["ms_per_step"]
+        alg1["multigrid_speedup"] = round(alg1["ms_per_step"] / out["ms_per_step"], 1)
+        out["algorithm1_no_multigrid"] = alg1
+        # the served speed-up on a saturated stream of 24 requests (each also
+        # solved alone in FP64 for the comparison)
+        out["speedups_over_fp64_alone"] = speedups_over_fp64_alone(out["batched"], args.serve_rate, 24)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -265,10 +265,33 @@ bp_status bp_autotune(bp_solver *s, int32_t steps, bp_tuning *out);
  * as one captured graph: which = 0 finest-level smoothing sweep, 1 finest-level
  * residual/restriction, 2 flow step, 3 explicit force, 4 the finest level's
  * multi-application smoothing launch of the time-step schedule (two or four
- * applications).  *bytes receives the algorithmic HBM bytes
- * of one launch (each value the kernel must read or write, once).  The state
- * is left unchanged. */
+ * applications).  *bytes receives the algorithmic HBM bytes of one launch:
+ * each value the kernel must read or write, once per application (the
+ * multi-application launch counts each of its applications).  The state is
+ * left unchanged (the smoothing launches' input buffer is not written). */
 bp_status bp_time_kernel(bp_solver *s, int32_t which, int32_t iters, double *avg_us, double *bytes);
+
+/* Where a time step's device time goes (measurement of Algorithm 5 as this
+ * library schedules it).  Runs `steps` fixed-cycle time steps (they advance
+ * the solver like bp_step) with the step's kernels launched directly and a
+ * HIP event before every launch; the table has one row per kernel variant
+ * and multigrid depth, in order of first launch: launches per step, device
+ * time per step (from the launch's event to the next one, so launch gaps
+ * are included), and algorithmic bytes per step (each value an application
+ * must read or write, once per application: a pair launch counts two
+ * applications).  *n_out receives the number of rows; at most cap are
+ * written. */
+typedef struct {
+  char name[48];            /* e.g. "pair shift f32", "quad+restrict f32", "tail", "flow" */
+  int32_t depth;            /* multigrid depth of a sweep or the tail's top (0 = finest), else -1 */
+  int32_t launches;         /* launches per step */
+  double us_per_step;       /* device microseconds per step */
+  double bytes_per_step;    /* algorithmic bytes per step */
+} bp_kernel_stat;
+bp_status bp_profile_step(bp_solver *s, int32_t steps, bp_kernel_stat *out, int32_t cap, int32_t *n_out);
+/* the same for a batch (declared below): its time steps' kernels */
+typedef struct bp_batch bp_batch;
+bp_status bp_batch_profile_step(bp_batch *b, int32_t steps, bp_kernel_stat *out, int32_t cap, int32_t *n_out);
 
 /* Plain device copy of `bytes` (multiple of 16) on a stream; used to calibrate
  * hardware byte counters. */
@@ -303,7 +326,6 @@ bp_status bp_create_static(const bp_problem *p, void *hip_stream, bp_solver **ou
  * the restriction and picks the region width of four applications with the
  * restriction according to the cells it covers in all), and otherwise
  * agree to rounding (operations are fused differently in the variants). */
-typedef struct bp_batch bp_batch;
 /* A problem whose state diverges (BP_ERR_DIVERGED above) leaves the batch at
  * the next check (every 8 steps of bp_batch_step, and at its end): its later
  * steps are not run, its fields stay those of the check, bp_batch_get_fields

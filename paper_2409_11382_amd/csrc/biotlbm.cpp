@@ -628,6 +628,8 @@ struct Op {
   TailL tl{};
   int count = 0;          // tiles / problems
   bool alt = false;       // multi-application launch: the alternative region
+  int set = 0;            // sweeps: the tile-list set (engine_upload)
+  int group = 0;          // sweeps: the storage group of the tile list
 };
 
 // tile-list key of a depth: full set or restriction set, one of three
@@ -878,6 +880,8 @@ void add_sweeps(Engine& E, std::vector<Op>& ops, int d, int set, int mode, int i
     o.sw.prolong = prolong;
     o.sw.partials = partials;
     o.count = cnt;
+    o.set = set;
+    o.group = g;
     ops.push_back(o);
   }
 }
@@ -1583,6 +1587,114 @@ bp_status diverged_probs(Engine& E, std::vector<Prob*>& out) {
 // steps between divergence checks of batches and servers
 constexpr int kDivCheckSteps = 8;
 
+// ---- per-launch profile of a time step (bp_profile_step)
+// cells an op covers: the level at its depth of every problem in its tile list
+double op_cells(const Engine& E, const Op& o, int depth) {
+  double cells = 0.0;
+  for (const Prob* P : E.probs) {
+    const int l = P->L - depth;
+    if (l < 1) continue;
+    const int td = P->lo.tail_depth;
+    if (o.kind == OP_SWEEP) {
+      const int set = o.set;
+      if ((set < 4 && (set & 1) && l < 2) || tgroup(E, *P, depth) != o.group) continue;
+      if ((set < 2 || set >= kSetFused) && td > 0 && depth >= td) continue;
+    }
+    cells += (double)P->lo.lv[l].nx * P->lo.lv[l].ny;
+  }
+  return cells;
+}
+
+// algorithmic bytes of one launch: every value an application must read or
+// write, once per application (SoA planes; s bytes per population value)
+double op_bytes(const Engine& E, const Op& o) {
+  const double s = E.fdbl ? 8.0 : 4.0;
+  const bool sh = E.shift;
+  switch (o.kind) {
+    case OP_SWEEP: {
+      const int d = o.sw.depth;
+      const double cells = op_cells(E, o, d);
+      const double ts = o.tdbl ? 8.0 : 4.0, cs = o.cdbl ? 8.0 : 4.0;
+      // per application: populations in and out, and the finest level's
+      // explicit force and displacement reference, or a coarse level's rhs
+      const double extra = d == 0 ? (2.0 + (sh ? 2.0 : 0.0)) * s : 8.0 * ts;
+      const double app = 16.0 * ts + extra;
+      const bool res = o.apps == 3 || o.apps == 5 || o.mode == kRestrict;
+      const int napps = o.mode == kRestrict ? 0 : (o.apps == 3 ? 2 : (o.apps == 5 ? 4 : o.apps));
+      double b = cells * napps * app;
+      if (res) b += cells * (8.0 * ts + extra + 2.0 * cs);  // the residual's sweep, restricted 4:1
+      if (o.sw.prolong && d + 1 < E.maxL) b += cells * 2.0 * cs;
+      if (o.sw.rebase_out) b += cells * 2.0 * 2.0 * s;
+      return b;
+    }
+    case OP_TAIL: {
+      // the levels of the tail, each application's populations and rhs once
+      double b = 0.0;
+      for (const Prob* P : E.probs) {
+        if (P->lo.tail_depth != o.tl.depth || o.tl.depth == 0) continue;
+        for (int l = 1; l <= P->L - o.tl.depth; ++l) {
+          const double n = (double)P->lo.lv[l].nx * P->lo.lv[l].ny, ls = P->lo.lv[l].dbl ? 8.0 : 4.0;
+          const int apps = l == 1 ? P->d.csweeps : 2 * E.K + 1;
+          b += n * apps * 24.0 * ls;
+        }
+      }
+      return b;
+    }
+    case OP_FLOW: {
+      double b = 0.0;
+      for (const Prob* P : E.probs)
+        b += (double)P->nx * P->ny * ((18.0 + 8.0 + (sh ? 1.0 : 0.0)) * s + 8.0 * 4.0 + (P->has_src ? 8.0 : 0.0) +
+                                      (P->d.omf ? 8.0 : 0.0));
+      return b;
+    }
+    case OP_FORCE:
+    case OP_REBASE:
+    case OP_REBASE_EL:
+    case OP_REBASE_FORCE: {
+      double b = 0.0;
+      for (const Prob* P : E.probs) {
+        const double n = (double)P->nx * P->ny;
+        const double force = (9.0 + 2.0) * s + 16.0 + (P->has_body ? 16.0 : 0.0) + (P->has_src ? 8.0 : 0.0) +
+                             (P->d.omf ? 8.0 : 0.0);
+        if (o.kind == OP_FORCE) b += n * force;
+        if (o.kind == OP_REBASE) b += n * (8.0 + 9.0 + 3.0) * 2.0 * s;
+        if (o.kind == OP_REBASE_EL) b += n * (8.0 + 2.0) * 2.0 * s;
+        if (o.kind == OP_REBASE_FORCE) b += n * ((8.0 + 9.0 + 3.0) * 2.0 * s + force);
+      }
+      return b;
+    }
+    default: return 0.0;
+  }
+}
+
+std::string op_name(const Op& o) {
+  switch (o.kind) {
+    case OP_SWEEP: {
+      std::string n;
+      switch (o.apps) {
+        case 2: n = "pair"; break;
+        case 3: n = "pair+restrict"; break;
+        case 4: n = "quad"; break;
+        case 5: n = "quad+restrict"; break;
+        default: n = o.mode == kRestrict ? "restrict" : "sweep"; break;
+      }
+      if (o.alt) n += " alt";
+      if (o.shift) n += " shift";
+      n += o.tdbl ? " f64" : " f32";
+      return n;
+    }
+    case OP_TAIL: return o.tl.full ? "tail whole" : (o.tl.shape ? "tail shaped" : "tail");
+    case OP_FLOW: return "flow";
+    case OP_FORCE: return "force";
+    case OP_REBASE: return "rebase";
+    case OP_REBASE_EL: return "rebase displacement";
+    case OP_REBASE_FORCE: return "rebase+force";
+    case OP_FINALIZE: return "finalize";
+    case OP_ADVANCE: return "advance";
+    default: return "other";
+  }
+}
+
 // ---- the static workspace of bp_create_static: one array per device, held
 // by the process until it ends.  In host code `scratch` names a host-side
 // stand-in, never a device address: the device address comes from
@@ -1619,6 +1731,76 @@ void scratch_release(int dev) {
   if (dev < 0 || dev >= kMaxDevices) return;
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   g_scratch_busy[dev] = false;
+}
+
+// the time-step ops of an engine, launched one by one with an event before
+// each (bp_profile_step, bp_batch_profile_step)
+bp_status profile_engine(Engine& E, int32_t steps, bp_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (steps < 1 || !n_out || (cap > 0 && !out)) return fail(BP_ERR_ARG, "bad arguments");
+  if (E.ne < 1) return fail(BP_ERR_ARG, "the profile runs fixed-cycle steps");
+  for (const Prob* P : E.probs)
+    if (P->status != BP_OK) return fail(BP_ERR_STATE, "a problem is in an error state");
+  std::vector<Op> ops;
+  build_step_ops(E, ops);
+  // one entry per (name, depth), in the order of first appearance
+  std::vector<std::string> names;
+  std::vector<int> depth_of, slot(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const std::string nm = op_name(ops[i]);
+    const int d = ops[i].kind == OP_SWEEP ? ops[i].sw.depth : (ops[i].kind == OP_TAIL ? ops[i].tl.depth : -1);
+    int k = 0;
+    while (k < (int)names.size() && !(names[k] == nm && depth_of[k] == d)) ++k;
+    if (k == (int)names.size()) {
+      names.push_back(nm);
+      depth_of.push_back(d);
+    }
+    slot[i] = k;
+  }
+  std::vector<double> us(names.size(), 0.0), bytes(names.size(), 0.0);
+  std::vector<int> launches(names.size(), 0);
+  for (size_t i = 0; i < ops.size(); ++i) {
+    bytes[slot[i]] += op_bytes(E, ops[i]);
+    launches[slot[i]] += 1;
+  }
+  std::vector<hipEvent_t> ev(ops.size() + 1, nullptr);
+  bp_status rc = BP_OK;
+  for (auto& e : ev)
+    if (rc == BP_OK && hipEventCreate(&e) != hipSuccess) rc = fail(BP_ERR_DEVICE, "hipEventCreate failed");
+  for (int k = 0; k < steps && rc == BP_OK; ++k) {
+    for (size_t i = 0; i < ops.size() && rc == BP_OK; ++i) {
+      if (hipEventRecord(ev[i], E.stream) != hipSuccess) rc = fail(BP_ERR_DEVICE, "hipEventRecord failed");
+      const hipError_t le = run_op(E, ops[i]);
+      if (le != hipSuccess) rc = fail(BP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
+    }
+    if (rc == BP_OK && (hipEventRecord(ev[ops.size()], E.stream) != hipSuccess ||
+                        hipEventSynchronize(ev[ops.size()]) != hipSuccess))
+      rc = fail(BP_ERR_DEVICE, "timing events failed");
+    for (size_t i = 0; i < ops.size() && rc == BP_OK; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) rc = fail(BP_ERR_DEVICE, "event time failed");
+      us[slot[i]] += 1000.0 * ms;
+    }
+    if (rc == BP_OK)
+      for (Prob* P : E.probs) {
+        P->step += 1;
+        P->last_ne = E.ne;
+        P->total_cycles += E.ne;
+      }
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc != BP_OK) return rc;
+  *n_out = (int32_t)names.size();
+  for (int k = 0; k < (int)names.size() && k < cap; ++k) {
+    bp_kernel_stat& o = out[k];
+    std::memset(&o, 0, sizeof(o));
+    std::strncpy(o.name, names[k].c_str(), sizeof(o.name) - 1);
+    o.depth = depth_of[k];
+    o.launches = launches[k];
+    o.us_per_step = us[k] / steps;
+    o.bytes_per_step = bytes[k];
+  }
+  return BP_OK;
 }
 
 }  // namespace
@@ -2185,8 +2367,8 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
   *avg_us = 1000.0 * ms / iters;
   double b;
   switch (which) {
-    case 0:
-    case 4: b = N * (16.0 + 2.0 + 2.0 * shift) * es; break;
+    case 0: b = N * (16.0 + 2.0 + 2.0 * shift) * es; break;
+    case 4: b = (quad_at(E, 0) ? 4.0 : 2.0) * N * (16.0 + 2.0 + 2.0 * shift) * es; break;
     case 1: {
       const double ce = P.lo.lv[P.L - 1].dbl ? 8.0 : 4.0;
       b = N * (8.0 + 2.0 + 2.0 * shift) * es + (N / 4.0) * 8.0 * ce;
@@ -2203,6 +2385,16 @@ bp_status bp_time_kernel(bp_solver* s, int32_t which, int32_t iters, double* avg
   }
   if (bytes) *bytes = b;
   return BP_OK;
+}
+
+bp_status bp_profile_step(bp_solver* s, int32_t steps, bp_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (!s) return fail(BP_ERR_ARG, "null solver");
+  return profile_engine(s->E, steps, out, cap, n_out);
+}
+
+bp_status bp_batch_profile_step(bp_batch* b, int32_t steps, bp_kernel_stat* out, int32_t cap, int32_t* n_out) {
+  if (!b) return fail(BP_ERR_ARG, "null batch");
+  return profile_engine(b->E, steps, out, cap, n_out);
 }
 
 bp_status bp_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {

@@ -69,6 +69,11 @@ class _Stats(C.Structure):
                 ("max_ratio", C.c_double), ("mean_ratio", C.c_double)]
 
 
+class _KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("depth", C.c_int32), ("launches", C.c_int32),
+                ("us_per_step", C.c_double), ("bytes_per_step", C.c_double)]
+
+
 _lib = None
 
 
@@ -103,6 +108,8 @@ def load_library():
             "bp_level_shape": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
             "bp_stats": [vp, C.POINTER(_Stats)],
             "bp_time_kernel": [vp, i32, i32, dp, dp],
+            "bp_profile_step": [vp, i32, C.POINTER(_KernelStat), i32, C.POINTER(i32)],
+            "bp_batch_profile_step": [vp, i32, C.POINTER(_KernelStat), i32, C.POINTER(i32)],
             "bp_get_tuning": [vp, C.POINTER(_Tuning)],
             "bp_set_tuning": [vp, C.POINTER(_Tuning)],
             "bp_autotune": [vp, i32, C.POINTER(_Tuning)],
@@ -329,6 +336,16 @@ class Solver:
         t = _tuning_struct(cur)
         _check(self._lib.bp_set_tuning(self._h, C.byref(t)), "bp_set_tuning")
 
+    def profile_step(self, steps=5, cap=256):
+        """bp_profile_step: per kernel variant and depth, launches, device
+        microseconds and algorithmic bytes per step (runs `steps` steps)."""
+        rows = (_KernelStat * cap)()
+        n = C.c_int32(0)
+        _check(self._lib.bp_profile_step(self._h, int(steps), rows, int(cap), C.byref(n)), "bp_profile_step")
+        return [{"name": rows[k].name.decode(), "depth": rows[k].depth, "launches": rows[k].launches,
+                 "us_per_step": rows[k].us_per_step, "bytes_per_step": rows[k].bytes_per_step}
+                for k in range(min(n.value, cap))]
+
     def time_kernel(self, which, iters=20):
         us, by = C.c_double(0), C.c_double(0)
         _check(self._lib.bp_time_kernel(self._h, int(which), int(iters), C.byref(us), C.byref(by)),
@@ -390,6 +407,16 @@ class Batch:
 
     def step(self, n=1):
         _check(self._lib.bp_batch_step(self._h, int(n)), "bp_batch_step")
+
+    def profile_step(self, steps=3, cap=256):
+        """bp_batch_profile_step (see Solver.profile_step)."""
+        rows = (_KernelStat * cap)()
+        n = C.c_int32(0)
+        _check(self._lib.bp_batch_profile_step(self._h, int(steps), rows, int(cap), C.byref(n)),
+               "bp_batch_profile_step")
+        return [{"name": rows[k].name.decode(), "depth": rows[k].depth, "launches": rows[k].launches,
+                 "us_per_step": rows[k].us_per_step, "bytes_per_step": rows[k].bytes_per_step}
+                for k in range(min(n.value, cap))]
 
     def autotune(self, steps=2):
         """Choose the launch-shape bounds by timing (before the first step;

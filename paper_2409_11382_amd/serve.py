@@ -55,19 +55,22 @@ def simulate(rate: float, count: int, seed=2, ws_gib=32.0, max_slots=512, nmin=1
                     failures.append({"request": idx, "error": str(e)})
                     out = None
                 done = time.perf_counter() - t0
-                lat.append(done - arr)
                 finish.append(done)
-                cell_steps += cells * nsteps
+                if out is not None:       # latency and throughput of completed solves only
+                    lat.append(done - arr)
+                    cell_steps += cells * nsteps
                 if keep_results:
                     results[idx] = out
     srv.close()
     makespan = max(finish) - reqs[0][0]
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.zeros(1)
     summary = {
-        "rate_per_s": rate, "requests": count,
-        "solves_per_s": round(count / makespan, 3),
+        "rate_per_s": rate, "requests": count, "completed": count - len(failures),
+        "solves_per_s": round((count - len(failures)) / makespan, 3),
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        # a 99th percentile needs about 100 samples; below that only the maximum is reported
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4) if len(lat) >= 100 else None,
+        "max_latency_s": round(float(lat.max()), 4),
         "mean_latency_s": round(float(lat.mean()), 4),
         "mlups": round(cell_steps / makespan / 1e6, 2),
         "peak_active": peak_active,
