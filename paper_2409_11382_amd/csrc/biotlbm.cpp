@@ -706,9 +706,10 @@ struct Engine {
   bool graph_valid = false, use_graph = true;
   // adaptive schedule (single-problem engines): its fixed pieces, each an op
   // list and, with a stream, a captured graph (AD_START: re-base, force and
-  // the stop flag's reset, AD_FIRST: the first V-cycle, AD_UNIT: re-base,
-  // measuring sweep, norms, stopping test and a later V-cycle, AD_END: flow
-  // step and counter, AD_UNITS: several units)
+  // the stop flag's reset, AD_FIRST: the first cycle, AD_UNIT: re-base and a
+  // later cycle whose first finest-level launch measures the norms, followed
+  // by the stopping test, AD_END: flow step and counter, AD_UNITS: several
+  // units)
   std::vector<Op> ad_ops[5];
   bool ad_loop = false;  // AD_FIRST runs every cycle of a step (whole-problem tail)
   hipGraphExec_t ad_graph[5] = {};
@@ -914,25 +915,13 @@ int add_smoothing(Engine& E, std::vector<Op>& ops, int d, int set, int count, in
   return sel;
 }
 
-// launches add_smoothing issues for `count` applications
-int smoothing_launches(int count, bool quad, bool fuse) {
-  int n = 0;
-  while (count > 0) {
-    count -= (quad && count % 4 == 0) ? 4 : ((fuse && count % 2 == 0) ? 2 : 1);
-    ++n;
-  }
-  return n;
-}
-
 // Algorithm 4 at depth d for every problem that has a level there.  The
 // iterate of a level starts in buffer A (zero at coarse depths) and ends in A
 // after its 2K smoothing applications (the pre- and post-smoothing runs take
-// the same number of launches).  first_done: the first pre-smoothing sweep was
-// already issued (adaptive mode).  tail: problems whose coarse tail starts at
+// the same number of launches).  tail: problems whose coarse tail starts at
 // this depth run it in one launch (time-step schedule); without it every level
 // is swept by the tile kernels (inspection operations).  fuse: several
-// smoothing applications per launch (after a separate first sweep only where
-// the launch count keeps the iterate ending in A).
+// smoothing applications per launch.
 // prolong_first: the first pre-smoothing application adds the coarser
 // depth's buffer A (the prolongated correction of full multigrid) to its
 // input.  A depth where every problem sits on its coarsest level takes the
@@ -942,9 +931,8 @@ void add_fmg_solve(Engine& E, std::vector<Op>& ops, int d1);
 
 // fmg: the coarse-grid correction is computed by full multigrid from zero
 // (add_fmg_solve) in place of the V-, W- or F-visit.
-void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool partials_last, bool tail = true,
-                bool fuse = false, int cyc = -1, bool from_zero = true, bool prolong_first = false,
-                bool fmg = false) {
+void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool partials_last, bool tail = true, bool fuse = false,
+                int cyc = -1, bool from_zero = true, bool prolong_first = false, bool fmg = false) {
   if (d >= E.maxL) return;
   if (cyc < 0) cyc = E.cycle;
   const int full = tail ? 0 : 2, restr = full + 1;
@@ -964,24 +952,12 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
   for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
   if (!here) return;
   fuse = fuse && tail;
-  bool fuse_here = fuse;
-  if (first_done && fuse) {
-    const bool q = quad_at(E, d);
-    if ((1 + smoothing_launches(E.K - 1, q, true) + smoothing_launches(E.K, q, true)) % 2 != 0) fuse_here = false;
-  }
   bool deeper = false;
   for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
   const int nsm = (!deeper && d > 0 && E.csweeps > 0) ? E.csweeps / 2 : E.K;  // pre- and post-smoothing steps
-  int sel = 0;
   bool restricted = false;
-  if (first_done) {
-    // the first pre-smoothing application (A -> B) was issued separately
-    sel = add_smoothing(E, ops, d, full, nsm - 1, 1, false, false, false, fuse_here, deeper && E.depth[d].fres,
-                        &restricted);
-  } else {
-    sel = add_smoothing(E, ops, d, full, nsm, 0, d > 0 && from_zero, prolong_first, false, fuse,
-                        deeper && E.depth[d].fres, &restricted);
-  }
+  int sel = add_smoothing(E, ops, d, full, nsm, 0, d > 0 && from_zero, prolong_first, false, fuse,
+                          deeper && E.depth[d].fres, &restricted);
   if (deeper) {
     if (!restricted) add_sweeps(E, ops, d, restr, kRestrict, sel, 0, 0, 0);
     // the coarse correction: one V-visit; W: two W-visits, F: an F-visit then
@@ -990,12 +966,12 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
     if (fmg) {
       add_fmg_solve(E, ops, d + 1);
     } else {
-      add_vcycle(E, ops, d + 1, false, false, tail, fuse, cyc, true);
-      if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_W, false);
-      if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, tail, fuse, BP_CYCLE_V, false);
+      add_vcycle(E, ops, d + 1, false, tail, fuse, cyc, true);
+      if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, tail, fuse, BP_CYCLE_W, false);
+      if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, tail, fuse, BP_CYCLE_V, false);
     }
   }
-  add_smoothing(E, ops, d, full, nsm, sel, false, true, partials_last && d == 0, fuse_here);
+  add_smoothing(E, ops, d, full, nsm, sel, false, true, partials_last && d == 0, fuse);
 }
 
 // Full multigrid (named as future work in the conclusion) for the coarse
@@ -1008,7 +984,7 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool first_done, bool pa
 // V-visit would leave it.  Every level runs on the tile kernels.
 void add_fmg_solve(Engine& E, std::vector<Op>& ops, int d1) {
   for (int d = d1; d + 1 < E.maxL; ++d) add_sweeps(E, ops, d, 3, kRestrict, 2, 0, 0, 0);
-  for (int d = E.maxL - 1; d >= d1; --d) add_vcycle(E, ops, d, false, false, false, false, BP_CYCLE_V, true, true);
+  for (int d = E.maxL - 1; d >= d1; --d) add_vcycle(E, ops, d, false, false, false, BP_CYCLE_V, true, true);
 }
 
 // Algorithm 1 with the lag of eq. source:implicit (one problem of one level,
@@ -1088,7 +1064,7 @@ void build_step_ops(Engine& E, std::vector<Op>& ops) {
   for (int j = 0; j < E.ne && !E.lag; ++j) {
     if (E.shift && j > 0 && j > fusable) ops.push_back(cell_op(E, OP_REBASE_EL));
     const size_t first = ops.size();
-    add_vcycle(E, ops, 0, false, j == E.ne - 1, true, E.fuse, -1, true, false, j == 0 && E.fmg);
+    add_vcycle(E, ops, 0, j == E.ne - 1, true, E.fuse, -1, true, false, j == 0 && E.fmg);
     for (size_t i = first; i < ops.size(); ++i)
       if (ops[i].kind == OP_SWEEP && ops[i].sw.depth == 0) ops[i].sw.eref_in = cur;
     if (j + 1 <= fusable) {
@@ -1284,13 +1260,15 @@ bp_status fixed_step(Engine& E) {
   return BP_OK;
 }
 
-// adaptive number of V-cycles (single-problem engines): before V-cycle j+1
-// (j >= 1) the first smoothing sweep also measures ||g - S(g)|| and ||g||; the
-// cycle is abandoned (the sweep's output discarded) once the ratio reaches the
-// tolerance or j reaches N_E,max.  The test runs on the device (in k_finalize)
-// and sets a stop flag that every launch of the following units checks, so
-// the host enqueues as many units (measuring sweep, test, cycle) as the last
-// step needed and reads the flag once; units past the stop do nothing.
+// adaptive number of V-cycles (single-problem engines): cycle j+1 (j >= 1)
+// starts with the fixed schedule's first finest-level launch, whose first
+// application also measures ||g_j - S(g_j)|| and ||g_j||; the stopping test
+// follows it, and the cycle is abandoned (that launch's output discarded)
+// once the ratio reaches the tolerance or j reaches N_E,max.  The test runs on
+// the device (in k_finalize) and sets a stop flag that every launch of the
+// following units checks, so the host enqueues as many units (cycle with its
+// test) as the last step needed and reads the flag once; units past the stop
+// do nothing.
 enum { AD_START, AD_FIRST, AD_UNIT, AD_END, AD_UNITS };
 constexpr int kAdUnits = 8;  // units per AD_UNITS graph (graph boundaries cost ~8 us each)
 
@@ -1343,25 +1321,36 @@ bp_status build_adaptive(Engine& E) {
     o.tl.tol = P.ne_tol;
     E.ad_ops[AD_FIRST].push_back(o);
   } else if (E.fmg) {
-    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse, -1, true, false, true);
+    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, true, E.fuse, -1, true, false, true);
   } else {
-    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, false, true, E.fuse);
+    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, true, E.fuse);
   }
   std::vector<Op>& u = E.ad_ops[AD_UNIT];
   if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
-  add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);
   Op fin = prob_op(E, OP_FINALIZE);  // the norms, then the stopping test
   fin.pl.decide = 1;
   fin.pl.tol = P.ne_tol;
   fin.pl.ne_max = P.ne_max;
-  u.push_back(fin);
-  set_skip(u, 0, P.d.ad);
-  const size_t c0 = u.size();
-  if (full)
+  if (full) {
+    add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);  // the measuring sweep, A -> B
+    u.push_back(fin);
     u.push_back(full_tail(1, E.K - 1));  // from the measuring sweep's output (B)
-  else
-    add_vcycle(E, u, 0, true, false, true, E.fuse);
-  set_skip(u, c0, P.d.ad);
+  } else {
+    // the cycle with the fixed schedule's launches; its first finest-level
+    // launch measures ||g - S(g)|| and ||g|| on its first application (the
+    // cycle's starting iterate), and the stopping test follows it.  On a stop
+    // the rest of the unit is skipped and that launch's output buffer (B) is
+    // dropped: the accepted iterate is still in A.
+    const size_t c0 = u.size();
+    add_vcycle(E, u, 0, false, true, E.fuse);
+    size_t i = c0;
+    while (i < u.size() && u[i].kind == OP_SWEEP && u[i].sw.depth == 0 && u[i].sw.in_sel == u[c0].sw.in_sel &&
+           u[i].sw.out_sel == u[c0].sw.out_sel && u[i].apps == u[c0].apps)
+      u[i++].sw.partials = u[c0].apps > 1 ? 2 : 1;  // one launch per storage group
+    fin.pl.fused = u[c0].apps > 1 ? 1 : 0;
+    u.insert(u.begin() + (std::ptrdiff_t)i, fin);
+  }
+  set_skip(u, 0, P.d.ad);
   E.ad_ops[AD_END].push_back(flow_op(E));
   E.ad_ops[AD_END].push_back(prob_op(E, OP_ADVANCE));
   for (int k = 0; k < kAdUnits; ++k) E.ad_ops[AD_UNITS].insert(E.ad_ops[AD_UNITS].end(), u.begin(), u.end());
@@ -2214,7 +2203,7 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
   bool zero = !fine;
   for (size_t k = 0; k < (size_t)8 * v.nx * v.ny && zero; ++k) zero = g[k] == 0.0;
   if (E.fmg) {
-    add_vcycle(E, ops, d, false, false, false, false, BP_CYCLE_V, false, false, true);
+    add_vcycle(E, ops, d, false, false, false, BP_CYCLE_V, false, false, true);
   } else if (E.lag) {
     // one cycle of Algorithm 1 (2K applications) as a time step starts it
     const int ne = E.ne;
@@ -2223,7 +2212,7 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
     E.ne = ne;
     for (auto& o : ops) o.sw.partials = 0;
   } else if (zero && d == P.lo.tail_depth) {
-    add_vcycle(E, ops, d, false, false, true);
+    add_vcycle(E, ops, d, false, true);
   } else {
     int sel = 0;
     for (int k = 0; k < E.K; ++k) {
@@ -2232,9 +2221,9 @@ bp_status bp_mg_cycle(bp_solver* s, int32_t level, double* g, const double* r, c
     }
     if (level > 1) {
       add_sweeps(E, ops, d, 3, kRestrict, sel, 0, 0, 0);
-      add_vcycle(E, ops, d + 1, false, false, false, false, E.cycle, true);
-      if (E.cycle == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, false, false, BP_CYCLE_W, false);
-      if (E.cycle == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, false, false, BP_CYCLE_V, false);
+      add_vcycle(E, ops, d + 1, false, false, false, E.cycle, true);
+      if (E.cycle == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, false, false, BP_CYCLE_W, false);
+      if (E.cycle == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, false, false, BP_CYCLE_V, false);
     }
     for (int k = 0; k < E.K; ++k) {
       add_sweeps(E, ops, d, 2, kSmooth, sel, 1 - sel, k == 0 ? 1 : 0, 0);

@@ -87,7 +87,8 @@ struct SweepL {
   int in_sel;     // 0: buffer A, 1: buffer B, 2: zero input
   int out_sel;    // 0: A, 1: B
   int prolong;    // add the coarse correction (coarser level's buffer A) to the input
-  int partials;   // write norm partials (finest level)
+  int partials;   // write norm partials (finest level): 1 of the last application's input,
+                  // 2 (multi-application launches) of the first application's input
   const int* skip;  // when set and *skip != 0 the launch does nothing (adaptive cycles past their stop)
   int eref_in;    // shifted storage: the displacement reference is eref (0) or eref2 (1)
   int rebase_out; // re-base the output on its displacement and write the new

@@ -651,6 +651,19 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
       }
       const bool out = pl && x >= 0 && x < nx && y >= 0 && y < ny && col >= H && col < RX - H &&
                        j >= H && j < RR - H;
+      if (a.partials == 2 && app == 0 && out) {
+        // the adaptive stopping test's norms of the launch's input, the
+        // iterate the cycle starts from: ||g - S(g)||^2 and ||g||^2
+        const double ex = SHIFT ? own_x() : 0.0, ey = SHIFT ? own_y() : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double rho = double(G[kk][q]) - double(gi[q]) * inv_gam;
+          double gf = double(G[kk][q]);
+          if (SHIFT) gf += el_geq<double>(q, ex, ey);
+          acc_r += rho * rho;
+          acc_g += gf * gf;
+        }
+      }
       if (RES && app == A - 1) {
         // residual of the smoothed iterate, summed over lane pairs (x, x + 1)
         // (both lanes of a pair lie in one row);
@@ -669,7 +682,7 @@ __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())
           for (int q = 0; q < 8; ++q) gout[q * plane + oidx] = G[kk][q];
         }
       } else if (!RES && app == A - 1) {
-        if (a.partials && out) {
+        if (a.partials == 1 && out) {
           const double ex = SHIFT ? own_x() : 0.0, ey = SHIFT ? own_y() : 0.0;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
