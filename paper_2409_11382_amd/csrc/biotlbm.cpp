@@ -515,8 +515,8 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.norm2 = (double*)(base + lo.off_scal);
   d.phase = (int*)(base + lo.off_scal + 32);
   d.flags = (int*)(base + lo.off_scal + 40);
-  d.ad_ratio = (double*)(base + lo.off_scal + 16);
   d.ad = (int*)(base + lo.off_scal + 48);
+  d.ad_ratio = (double*)(base + lo.off_scal + 56);  // right after ad: one read for both
   d.gref = (double*)(base + lo.off_scal + 64);
   for (int k = 0; k < 2; ++k) d.dlag[k] = lo.lag ? (void*)(base + lo.off_dlag[k]) : nullptr;
   d.ntiles_fine = lo.ntiles_fine;
@@ -705,14 +705,10 @@ struct Engine {
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
   // adaptive schedule (single-problem engines): its fixed pieces, each an op
-  // list and, with a stream, a captured graph (AD_START: re-base, force and
-  // the stop flag's reset, AD_FIRST: the first cycle, AD_UNIT: re-base and a
-  // later cycle whose first finest-level launch measures the norms, followed
-  // by the stopping test, AD_END: flow step and counter, AD_UNITS: several
-  // units)
-  std::vector<Op> ad_ops[5];
-  bool ad_loop = false;  // AD_FIRST runs every cycle of a step (whole-problem tail)
-  hipGraphExec_t ad_graph[5] = {};
+  // list and, with a stream, a captured graph (enum AdPiece below)
+  std::vector<Op> ad_ops[17];
+  bool ad_loop = false;  // AD_HEAD runs every cycle of a step (whole-problem tail)
+  hipGraphExec_t ad_graph[17] = {};
   bool ad_valid = false;
   bool xcd_order = true;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
@@ -1265,12 +1261,23 @@ bp_status fixed_step(Engine& E) {
 // application also measures ||g_j - S(g_j)|| and ||g_j||; the stopping test
 // follows it, and the cycle is abandoned (that launch's output discarded)
 // once the ratio reaches the tolerance or j reaches N_E,max.  The test runs on
-// the device (in k_finalize) and sets a stop flag that every launch of the
-// following units checks, so the host enqueues as many units (cycle with its
-// test) as the last step needed and reads the flag once; units past the stop
-// do nothing.
-enum { AD_START, AD_FIRST, AD_UNIT, AD_END, AD_UNITS };
-constexpr int kAdUnits = 8;  // units per AD_UNITS graph (graph boundaries cost ~8 us each)
+// the device (in k_finalize) and sets a stop flag that every later launch of
+// the step's cycles checks.  A unit is one test and the rest of its cycle.
+// The host predicts the tests a step needs (as many as the last step's), and
+// enqueues the units before the last one whole, then only the last one's
+// test, and reads the flag once: on the predicted stop no launch of an
+// abandoned cycle is enqueued; a stop earlier than predicted leaves launches
+// that return at once; a later one takes the rest of the unit and more units.
+enum AdPiece {
+  AD_HEAD,   // re-base, force, the stop flag's reset and the first cycle
+  AD_TEST,   // re-base, the first finest-level launch (norms) and the test
+  AD_REST,   // the rest of the cycle that a test let through
+  AD_END,    // flow step and step counter
+  AD_FULL8,  // eight units
+  AD_B1,     // AD_B1 + n - 1: n - 1 units and a test (n = 1 .. kAdUnits)
+};
+constexpr int kAdUnits = 8;  // graph boundaries cost ~8 us each
+static_assert(AD_B1 + kAdUnits <= 17, "adaptive pieces");
 
 void set_skip(std::vector<Op>& ops, size_t from, const int* flag) {
   for (size_t k = from; k < ops.size(); ++k) {
@@ -1290,9 +1297,14 @@ bp_status build_adaptive(Engine& E) {
   }
   E.ad_valid = false;
   for (auto& o : E.ad_ops) o.clear();
-  if (E.shift) E.ad_ops[AD_START].push_back(cell_op(E, OP_REBASE));
-  E.ad_ops[AD_START].push_back(cell_op(E, OP_FORCE));
-  E.ad_ops[AD_START].push_back(prob_op(E, OP_AD_RESET));
+  std::vector<Op>& head = E.ad_ops[AD_HEAD];
+  if (E.shift && !P.d.grad_central) {  // as in the fixed-cycle step
+    head.push_back(cell_op(E, OP_REBASE_FORCE));
+  } else {
+    if (E.shift) head.push_back(cell_op(E, OP_REBASE));
+    head.push_back(cell_op(E, OP_FORCE));
+  }
+  head.push_back(prob_op(E, OP_AD_RESET));
   // a problem whose finest level fits one workgroup runs each cycle (after
   // the stopping test) as one whole-problem tail launch; the cycle's result
   // ends in buffer A as the tile schedule's does
@@ -1319,43 +1331,46 @@ bp_status build_adaptive(Engine& E) {
     o.tl.loop = 1;
     o.tl.ne_max = P.ne_max;
     o.tl.tol = P.ne_tol;
-    E.ad_ops[AD_FIRST].push_back(o);
-  } else if (E.fmg) {
-    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, true, E.fuse, -1, true, false, true);
+    head.push_back(o);
   } else {
-    add_vcycle(E, E.ad_ops[AD_FIRST], 0, false, true, E.fuse);
-  }
-  std::vector<Op>& u = E.ad_ops[AD_UNIT];
-  if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
-  Op fin = prob_op(E, OP_FINALIZE);  // the norms, then the stopping test
-  fin.pl.decide = 1;
-  fin.pl.tol = P.ne_tol;
-  fin.pl.ne_max = P.ne_max;
-  if (full) {
-    add_sweeps(E, u, 0, 0, kSmooth, 0, 1, 0, 1);  // the measuring sweep, A -> B
-    u.push_back(fin);
-    u.push_back(full_tail(1, E.K - 1));  // from the measuring sweep's output (B)
-  } else {
-    // the cycle with the fixed schedule's launches; its first finest-level
+    if (E.fmg)
+      add_vcycle(E, head, 0, false, true, E.fuse, -1, true, false, true);
+    else
+      add_vcycle(E, head, 0, false, true, E.fuse);
+    // a later cycle with the fixed schedule's launches; its first finest-level
     // launch measures ||g - S(g)|| and ||g|| on its first application (the
     // cycle's starting iterate), and the stopping test follows it.  On a stop
-    // the rest of the unit is skipped and that launch's output buffer (B) is
-    // dropped: the accepted iterate is still in A.
+    // the rest is skipped and that launch's output buffer (B) is dropped: the
+    // accepted iterate is still in A.
+    std::vector<Op> u;
+    if (E.shift) u.push_back(cell_op(E, OP_REBASE_EL));  // as in the fixed-cycle step
     const size_t c0 = u.size();
     add_vcycle(E, u, 0, false, true, E.fuse);
     size_t i = c0;
     while (i < u.size() && u[i].kind == OP_SWEEP && u[i].sw.depth == 0 && u[i].sw.in_sel == u[c0].sw.in_sel &&
            u[i].sw.out_sel == u[c0].sw.out_sel && u[i].apps == u[c0].apps)
       u[i++].sw.partials = u[c0].apps > 1 ? 2 : 1;  // one launch per storage group
+    Op fin = prob_op(E, OP_FINALIZE);  // the norms, then the stopping test
+    fin.pl.decide = 1;
+    fin.pl.tol = P.ne_tol;
+    fin.pl.ne_max = P.ne_max;
     fin.pl.fused = u[c0].apps > 1 ? 1 : 0;
     u.insert(u.begin() + (std::ptrdiff_t)i, fin);
+    set_skip(u, 0, P.d.ad);
+    E.ad_ops[AD_TEST].assign(u.begin(), u.begin() + (std::ptrdiff_t)i + 1);
+    E.ad_ops[AD_REST].assign(u.begin() + (std::ptrdiff_t)i + 1, u.end());
+    for (int k = 0; k < kAdUnits; ++k) E.ad_ops[AD_FULL8].insert(E.ad_ops[AD_FULL8].end(), u.begin(), u.end());
+    for (int n = 1; n <= kAdUnits; ++n) {
+      std::vector<Op>& b = E.ad_ops[AD_B1 + n - 1];
+      for (int k = 0; k + 1 < n; ++k) b.insert(b.end(), u.begin(), u.end());
+      b.insert(b.end(), E.ad_ops[AD_TEST].begin(), E.ad_ops[AD_TEST].end());
+    }
   }
-  set_skip(u, 0, P.d.ad);
   E.ad_ops[AD_END].push_back(flow_op(E));
   E.ad_ops[AD_END].push_back(prob_op(E, OP_ADVANCE));
-  for (int k = 0; k < kAdUnits; ++k) E.ad_ops[AD_UNITS].insert(E.ad_ops[AD_UNITS].end(), u.begin(), u.end());
   if (E.use_graph && E.stream)
-    for (int k = 0; k < 5; ++k) BPCHK(capture_ops(E, E.ad_ops[k], &E.ad_graph[k]));
+    for (int k = 0; k < AD_B1 + kAdUnits; ++k)
+      if (!E.ad_ops[k].empty()) BPCHK(capture_ops(E, E.ad_ops[k], &E.ad_graph[k]));
   E.ad_valid = true;
   return BP_OK;
 }
@@ -1368,33 +1383,36 @@ bp_status run_adaptive(Engine& E, int k) {
   return run_ops(E, E.ad_ops[k]);
 }
 
+// the stop flag, the cycle count and the last ratio (adjacent on the device)
+bp_status read_stop(Engine& E, const Prob& P) {
+  HIPCHK(hipMemcpyAsync(E.host_pin, P.d.ad, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, E.stream));
+  HIPCHK(hipStreamSynchronize(E.stream));
+  return BP_OK;
+}
+
 bp_status adaptive_step(Engine& E) {
   Prob& P = *E.probs[0];
   if (!E.ad_valid) BPCHK(build_adaptive(E));
-  BPCHK(run_adaptive(E, AD_START));
-  BPCHK(run_adaptive(E, AD_FIRST));
-  // a step takes at most N_E,max units (the last one only tests)
-  const int cap = std::max(1, P.ne_max);
-  int batch = std::min(cap, P.last_ne > 0 ? P.last_ne : 8);
-  int issued = 0;
+  BPCHK(run_adaptive(E, AD_HEAD));
   int* st = (int*)E.host_pin;
-  for (;;) {
-    if (E.ad_loop) {  // the whole-problem tail ran every cycle and test
-      HIPCHK(hipMemcpyAsync(st, P.d.ad, 2 * sizeof(int), hipMemcpyDeviceToHost, E.stream));
-      HIPCHK(hipMemcpyAsync(E.host_pin + 1, P.d.ad_ratio, sizeof(double), hipMemcpyDeviceToHost, E.stream));
-      HIPCHK(hipStreamSynchronize(E.stream));
-      if (st[0] == 0) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
-      break;
+  if (E.ad_loop) {  // the whole-problem tail ran every cycle and test
+    BPCHK(read_stop(E, P));
+    if (st[0] == 0) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
+  } else {
+    // a step takes at most N_E,max tests (the last one stops)
+    const int cap = std::max(1, P.ne_max);
+    int want = std::min(cap, P.last_ne > 0 ? P.last_ne : 8);
+    int issued = 0;
+    for (;;) {
+      for (; want > kAdUnits; want -= kAdUnits, issued += kAdUnits) BPCHK(run_adaptive(E, AD_FULL8));
+      BPCHK(run_adaptive(E, AD_B1 + want - 1));
+      issued += want;
+      BPCHK(read_stop(E, P));
+      if (st[0] != 0) break;
+      if (issued >= cap) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
+      BPCHK(run_adaptive(E, AD_REST));  // the cycle that the last test let through
+      want = std::min(4, cap - issued);
     }
-    for (int k = 0; k + kAdUnits <= batch; k += kAdUnits) BPCHK(run_adaptive(E, AD_UNITS));
-    for (int k = 0; k < batch % kAdUnits; ++k) BPCHK(run_adaptive(E, AD_UNIT));
-    issued += batch;
-    HIPCHK(hipMemcpyAsync(st, P.d.ad, 2 * sizeof(int), hipMemcpyDeviceToHost, E.stream));
-    HIPCHK(hipMemcpyAsync(E.host_pin + 1, P.d.ad_ratio, sizeof(double), hipMemcpyDeviceToHost, E.stream));
-    HIPCHK(hipStreamSynchronize(E.stream));
-    if (st[0] != 0) break;
-    if (issued >= cap) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
-    batch = std::min(4, cap - issued);
   }
   if (st[0] == 2) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
   const int j = st[1];
