@@ -290,7 +290,8 @@ def batched(steps, warmup, count=256, tune=True):
         nb = k["MB_per_step"] * 1e6 / k["launches"]
         out["roofline"] = {"bound": "hbm", "achieved": round(nb / (us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                           "traffic": None, "kernel": "k_tsweep2 finest-level pair (" + k["kernel"] + ")",
+                           "traffic": measured_traffic(PMC_STEP_BATCH, "pair_hbm_bytes_per_launch"),
+                           "kernel": "k_tsweep2 finest-level pair (" + k["kernel"] + ")",
                            "avg_us": round(us, 3), "bytes_per_launch": nb,
                            "share_of_step": fine_pair_share(brk)}
     b.close()
