@@ -101,8 +101,11 @@ def step_bytes_per_cell(p, fp64: bool, shifted: bool):
     force = (9 + 2) * s + 2 * 8
     flow = 18 * s + 3 * 8
     extract = 8
-    # step start, then the new displacement reference written between cycles
-    rebase = ((17 + 3) * 2 + (ne - 1) * 2) * s if shifted else 0.0
+    # shifted storage: the displacement re-base at the step start (8
+    # populations, 2 reference values, read and written), the pressure
+    # reference read and written by the flow step that re-bases its output,
+    # and the new displacement reference written between cycles
+    rebase = ((8 + 2) * 2 + 2 + (ne - 1) * 2) * s if shifted else 0.0
     return ne * per_cycle + force + flow + extract + rebase
 
 

@@ -145,7 +145,7 @@ struct Layout {
   int cycle = BP_CYCLE_V;
   bool full_tail = false;    // the whole problem fits one workgroup (adaptive cycles)
   std::vector<LevelLay> lv;  // 1..L
-  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref;
+  size_t off_f[2], off_D[3], off_pout, off_fbody, off_src, off_omf, off_Ft, off_eref, off_eref2, off_pref[2];
   size_t off_eta, off_sig, off_part, off_part2, off_scal, off_ttab, off_addt, off_elbc[4], off_ftype[4], off_flbc[4];
   size_t off_dlag[2] = {SIZE_MAX, SIZE_MAX};
   bool lag = false;
@@ -216,7 +216,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
   const size_t rs = lo.ref64 ? 8 : 4;
   lo.off_eref = lo.shift ? take(2 * lo.plane * rs) : SIZE_MAX;
   lo.off_eref2 = lo.shift ? take(2 * lo.plane * rs) : SIZE_MAX;
-  lo.off_pref = lo.shift ? take(lo.plane * rs) : SIZE_MAX;
+  for (int k = 0; k < 2; ++k) lo.off_pref[k] = lo.shift ? take(lo.plane * rs) : SIZE_MAX;
   const size_t N = (size_t)p->nx * p->ny;
   lo.off_eta = take(2 * N * 8);
   lo.off_sig = take(3 * N * 8);
@@ -506,7 +506,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
   d.eref = lo.shift ? (void*)(base + lo.off_eref) : nullptr;
   d.eref2 = lo.shift ? (void*)(base + lo.off_eref2) : nullptr;
   d.ref64 = lo.ref64 ? 1 : 0;
-  d.pref = lo.shift ? (void*)(base + lo.off_pref) : nullptr;
+  for (int k = 0; k < 2; ++k) d.pref[k] = lo.shift ? (void*)(base + lo.off_pref[k]) : nullptr;
   d.eta = (double*)(base + lo.off_eta);
   d.sig = (double*)(base + lo.off_sig);
   d.partials = (double*)(base + lo.off_part);
@@ -613,7 +613,7 @@ bp_status setup_problem(const bp_problem* p, const Layout& lo, char* base, hipSt
 }
 
 // ---------------------------------------------------------------- engine
-enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE, OP_REBASE_EL, OP_REBASE_FORCE, OP_AD_RESET, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
+enum OpKind { OP_SWEEP, OP_TAIL, OP_FORCE, OP_REBASE_EL, OP_REBASE_FORCE, OP_AD_RESET, OP_FLOW, OP_FINALIZE, OP_ADVANCE, OP_INIT, OP_EXTRACT };
 
 struct Op {
   OpKind kind;
@@ -1038,17 +1038,9 @@ Op flow_op(Engine& E) {
 // step ends on buffer eref; a remaining boundary takes the re-basing kernel.
 void build_step_ops(Engine& E, std::vector<Op>& ops) {
   ops.clear();
-  // the step-start re-base and the explicit force share a pass over the cells
-  // unless a problem takes the central pressure gradient, which reads the
-  // neighbours' populations that the re-base rewrites
-  bool central = false;
-  for (auto* P : E.probs) central = central || P->d.grad_central;
-  if (E.shift && !central) {
-    ops.push_back(cell_op(E, OP_REBASE_FORCE));
-  } else {
-    if (E.shift) ops.push_back(cell_op(E, OP_REBASE));
-    ops.push_back(cell_op(E, OP_FORCE));
-  }
+  // the step-start displacement re-base and the explicit force share a pass
+  // over the cells (the previous flow step re-based the pressure)
+  ops.push_back(cell_op(E, E.shift ? OP_REBASE_FORCE : OP_FORCE));
   const int fusable = (E.shift && E.fuse && E.K >= 2 && !E.lag) ? 2 * ((E.ne - 1) / 2) : 0;
   int cur = 0;  // reference buffer of the cycle
   if (E.lag) {
@@ -1131,11 +1123,8 @@ hipError_t run_op(const Engine& E, const Op& o) {
     case OP_FORCE: return E.fdbl ? launch_force<double>(o.cl, o.count, s) : launch_force<float>(o.cl, o.count, s);
     case OP_REBASE_FORCE:
       return E.fdbl ? launch_rebase_force<double>(o.cl, o.count, s) : launch_rebase_force<float>(o.cl, o.count, s);
-    case OP_REBASE:
-    case OP_REBASE_EL: {
-      const bool flow = o.kind == OP_REBASE;
-      return E.fdbl ? launch_rebase<double>(o.cl, o.count, flow, s) : launch_rebase<float>(o.cl, o.count, flow, s);
-    }
+    case OP_REBASE_EL:
+      return E.fdbl ? launch_rebase<double>(o.cl, o.count, s) : launch_rebase<float>(o.cl, o.count, s);
     case OP_INIT: return E.fdbl ? launch_init<double>(o.cl, o.count, s) : launch_init<float>(o.cl, o.count, s);
     case OP_FLOW:
       if (E.fdbl) return E.shift ? launch_tflow<double, true>(o.cl, o.count, s) : launch_tflow<double, false>(o.cl, o.count, s);
@@ -1298,12 +1287,7 @@ bp_status build_adaptive(Engine& E) {
   E.ad_valid = false;
   for (auto& o : E.ad_ops) o.clear();
   std::vector<Op>& head = E.ad_ops[AD_HEAD];
-  if (E.shift && !P.d.grad_central) {  // as in the fixed-cycle step
-    head.push_back(cell_op(E, OP_REBASE_FORCE));
-  } else {
-    if (E.shift) head.push_back(cell_op(E, OP_REBASE));
-    head.push_back(cell_op(E, OP_FORCE));
-  }
+  head.push_back(cell_op(E, E.shift ? OP_REBASE_FORCE : OP_FORCE));  // as in the fixed-cycle step
   head.push_back(prob_op(E, OP_AD_RESET));
   // a problem whose finest level fits one workgroup runs each cycle (after
   // the stopping test) as one whole-problem tail launch; the cycle's result
@@ -1650,12 +1634,11 @@ double op_bytes(const Engine& E, const Op& o) {
     case OP_FLOW: {
       double b = 0.0;
       for (const Prob* P : E.probs)
-        b += (double)P->nx * P->ny * ((18.0 + 8.0 + (sh ? 1.0 : 0.0)) * s + 8.0 * 4.0 + (P->has_src ? 8.0 : 0.0) +
+        b += (double)P->nx * P->ny * ((18.0 + 8.0 + (sh ? 2.0 : 0.0)) * s + 8.0 * 4.0 + (P->has_src ? 8.0 : 0.0) +
                                       (P->d.omf ? 8.0 : 0.0));
       return b;
     }
     case OP_FORCE:
-    case OP_REBASE:
     case OP_REBASE_EL:
     case OP_REBASE_FORCE: {
       double b = 0.0;
@@ -1664,9 +1647,8 @@ double op_bytes(const Engine& E, const Op& o) {
         const double force = (9.0 + 2.0) * s + 16.0 + (P->has_body ? 16.0 : 0.0) + (P->has_src ? 8.0 : 0.0) +
                              (P->d.omf ? 8.0 : 0.0);
         if (o.kind == OP_FORCE) b += n * force;
-        if (o.kind == OP_REBASE) b += n * (8.0 + 9.0 + 3.0) * 2.0 * s;
         if (o.kind == OP_REBASE_EL) b += n * (8.0 + 2.0) * 2.0 * s;
-        if (o.kind == OP_REBASE_FORCE) b += n * ((8.0 + 9.0 + 3.0) * 2.0 * s + force);
+        if (o.kind == OP_REBASE_FORCE) b += n * ((8.0 + 2.0) * 2.0 * s + force);
       }
       return b;
     }
@@ -1693,7 +1675,6 @@ std::string op_name(const Op& o) {
     case OP_TAIL: return o.tl.full ? "tail whole" : (o.tl.shape ? "tail shaped" : "tail");
     case OP_FLOW: return "flow";
     case OP_FORCE: return "force";
-    case OP_REBASE: return "rebase";
     case OP_REBASE_EL: return "rebase displacement";
     case OP_REBASE_FORCE: return "rebase+force";
     case OP_FINALIZE: return "finalize";
@@ -2093,7 +2074,7 @@ bp_status bp_get_state(bp_solver* s, double* f, double* g, double* D1, double* D
   if (P.lo.shift) {
     pr.resize(N);
     er.resize(2 * N);
-    BPCHK(down(st, P.lo.ref64, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
+    BPCHK(down(st, P.lo.ref64, P.d.pref[n & 1], nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
     BPCHK(down(st, P.lo.ref64, P.d.eref, nx, ny, P.lo.pitch, P.lo.plane, er.data(), 2));
   }
   if (f) {
@@ -2157,7 +2138,7 @@ bp_status bp_set_state(bp_solver* s, const double* f, const double* g, const dou
         pr[k] = to_ref(sum);
         for (int i = 0; i < 9; ++i) df[i * N + k] = f[i * N + k] - W9[i] * pr[k];
       }
-      BPCHK(up(st, P.lo.ref64, P.d.pref, nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
+      BPCHK(up(st, P.lo.ref64, P.d.pref[n & 1], nx, ny, P.lo.pitch, P.lo.plane, pr.data(), 1));
       BPCHK(up(st, P.lo.fdbl, P.d.f[n & 1], nx, ny, P.lo.pitch, P.lo.plane, df.data(), 9));
     }
   } else {

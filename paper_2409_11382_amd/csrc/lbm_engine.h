@@ -50,7 +50,8 @@ struct ProbD {
   void* eref;                 // displacement reference (shifted storage) or null
   void* eref2;                // its second buffer, written by a re-basing sweep
   int ref64;                  // references (eref, eref2, pref) in FP64, else FP32
-  void* pref;                 // pressure reference (shifted storage) or null
+  void* pref[2];              // pressure reference (shifted storage) or null: the populations
+                              // f[n & 1] of step n are offsets from pref[n & 1]
   double* eta;                // extraction output (2 dense planes)
   double* sig;                // extraction output (3 dense planes)
   double* partials;           // per finest-level tile: sum rho^2, sum g^2
@@ -219,9 +220,9 @@ hipError_t launch_force(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
 hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s);
 template <typename T>
-hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s);
-// the step-start re-base followed by the explicit force with the first-moment
-// pressure gradient, in one pass over the cells
+hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s);
+// the step-start displacement re-base and the step's explicit force (either
+// pressure gradient), in one pass over the cells
 template <typename T>
 hipError_t launch_rebase_force(const CellL& a, int ntiles, hipStream_t s);
 template <typename T, bool SHIFT>

@@ -820,7 +820,8 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
   const bool col_ok = x >= -1 && x < nx + 1;
   const int gx = col_ok ? ghost_map(x, nx, perx) : 0;
   const bool out_lane = lane >= kHalo && lane < kWave - kHalo && x < nx;
-  void* pref = SHIFT ? P.pref : nullptr;
+  void* pref = SHIFT ? P.pref[n & 1] : nullptr;
+  void* pref_next = SHIFT ? P.pref[(n + 1) & 1] : nullptr;
   const bool r64 = P.ref64 != 0;
 
 #pragma unroll
@@ -955,6 +956,20 @@ __global__ __launch_bounds__(256) void k_tflow(CellL a) {
       }
     }
     const int64_t idx = (int64_t)y * pitch + x;
+    if (SHIFT) {
+      // the next step's re-base of the pressure: its zeroth moment moves into
+      // the reference, written to the other buffer (neighbours of this launch
+      // still read this step's)
+      T pl = T(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) pl += fo[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fo[i] -= T(w9(i)) * pl;
+      if (r64)
+        ((double*)pref_next)[idx] = p0 + double(pl);
+      else
+        ((float*)pref_next)[idx] = float(p0) + float(pl);
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) fout[i * plane + idx] = fo[i];
   }
@@ -1000,7 +1015,7 @@ __device__ __forceinline__ void force_stage(const ProbD& P, const LevelD& V, int
   const double* D1 = P.D[(n + 2) % 3];
   const double* D2 = P.D[(n + 1) % 3];
   const T* f = (const T*)P.f[n & 1];
-  const void* pref = P.pref;
+  const void* pref = P.pref[n & 1];
   const bool r64 = P.ref64 != 0;
   const bool perx = P.el[kLeft] == kElPeriodic, pery = P.el[kBottom] == kElPeriodic;
   for (int r = threadIdx.x; r < kFRX * kFRY; r += blockDim.x) {
@@ -1058,22 +1073,12 @@ __device__ __forceinline__ void force_moments(const ProbD& P, const LevelD& V, c
   py = -3.0 * om * jy;
 }
 
+// the force of this thread's cell from the staged planes: the source part's
+// gradient, and the pressure gradient (central: from the staged pressure;
+// else from the first moments of the cell's own populations)
 template <typename T>
-__global__ __launch_bounds__(256) void k_force(CellL a) {
-  __shared__ double sst[kFRY][kFRX];
-  __shared__ double sp[kFRY][kFRX];
-  const int2 te = a.tiles[blockIdx.x];
-  const ProbD& P = a.probs[te.x];
-  const LevelD& V = P.lv[P.L];
-  const int n = *P.phase;
-  const bool central = P.grad_central != 0;  // one problem per block
-  if (central)
-    force_stage<T, true>(P, V, te.y, n, sst, sp);
-  else
-    force_stage<T, false>(P, V, te.y, n, sst, sp);
-  __syncthreads();
-  const CellPos c = cell_pos(V, te.y);
-  if (!c.in) return;
+__device__ __forceinline__ void force_finish(const ProbD& P, const LevelD& V, const CellPos& c, int n, bool central,
+                                             const double (*sst)[kFRX], const double (*sp)[kFRX]) {
   double v[3][3], gx, gy, px, py;
   force_gather(sst, v);
   grad_c(v, gx, gy);
@@ -1093,6 +1098,25 @@ __global__ __launch_bounds__(256) void k_force(CellL a) {
     force_moments(P, V, c, jx, jy, px, py);
   }
   force_write<T>(P, V, c, gx, gy, px, py);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_force(CellL a) {
+  __shared__ double sst[kFRY][kFRX];
+  __shared__ double sp[kFRY][kFRX];
+  const int2 te = a.tiles[blockIdx.x];
+  const ProbD& P = a.probs[te.x];
+  const LevelD& V = P.lv[P.L];
+  const int n = *P.phase;
+  const bool central = P.grad_central != 0;  // one problem per block
+  if (central)
+    force_stage<T, true>(P, V, te.y, n, sst, sp);
+  else
+    force_stage<T, false>(P, V, te.y, n, sst, sp);
+  __syncthreads();
+  const CellPos c = cell_pos(V, te.y);
+  if (!c.in) return;
+  force_finish<T>(P, V, c, n, central, sst, sp);
 }
 
 // initial conditions (eqs. ICs, ICs:moments with p = 0 and eta = 0 at t = 0)
@@ -1141,27 +1165,38 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
   if (P.eref && P.ref64) {
     ((double*)P.eref)[idx] = 0.0;
     ((double*)P.eref)[V.plane + idx] = 0.0;
-    ((double*)P.pref)[idx] = 0.0;
+    ((double*)P.pref[0])[idx] = 0.0;
+    ((double*)P.pref[1])[idx] = 0.0;
   } else if (P.eref) {
     ((float*)P.eref)[idx] = 0.f;
     ((float*)P.eref)[V.plane + idx] = 0.f;
-    ((float*)P.pref)[idx] = 0.f;
+    ((float*)P.pref[0])[idx] = 0.f;
+    ((float*)P.pref[1])[idx] = 0.f;
   }
   P.pout[idx] = 0.0;
 }
 
-// re-basing of the shifted storage: move the per-cell references to the
-// current displacement (and, with FLOW, pressure) so the stored offsets stay
-// small
-template <typename T, bool FLOW, bool FORCE = false>
+// re-basing of the shifted storage: move the per-cell displacement reference
+// to the current displacement so the stored offsets stay small (the pressure
+// is re-based by the flow step that writes the populations).  FORCE: the
+// step's explicit force in the same pass; it reads the populations and the
+// pressure reference, which this kernel leaves alone, so the central gradient
+// may read any neighbour.
+template <typename T, bool FORCE>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
   if (a.skip && *a.skip) return;  // uniform over the grid
   __shared__ double sst[FORCE ? kFRY : 1][kFRX];
+  __shared__ double sp[FORCE ? kFRY : 1][kFRX];
   const int2 te = a.tiles[blockIdx.x];
   const ProbD& P = a.probs[te.x];
   const LevelD& V = P.lv[P.L];
-  if (FORCE) {  // the force's source part (the re-base leaves the D fields alone)
-    force_stage<T, false>(P, V, te.y, *P.phase, sst, nullptr);
+  const int n = FORCE ? *P.phase : 0;
+  const bool central = FORCE && P.grad_central != 0;  // one problem per block
+  if (FORCE) {
+    if (central)
+      force_stage<T, true>(P, V, te.y, n, sst, sp);
+    else
+      force_stage<T, false>(P, V, te.y, n, sst, sp);
     __syncthreads();
   }
   const CellPos c = cell_pos(V, te.y);
@@ -1184,38 +1219,7 @@ __global__ __launch_bounds__(256) void k_rebase(CellL a) {
     eref[idx] += float(m10);
     eref[V.plane + idx] += float(m01);
   }
-  if (!FLOW) return;
-  T* f = (T*)P.f[(*P.phase) & 1];
-  T fv[9];
-  T p = T(0);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    fv[i] = f[i * V.plane + idx];
-    p += fv[i];
-  }
-  double jx = 0.0, jy = 0.0;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T v = fv[i] - T(w9(i)) * p;
-    f[i * V.plane + idx] = v;
-    if (FORCE && i > 0) {
-      jx += double(v) * cx9(i);
-      jy += double(v) * cy9(i);
-    }
-  }
-  if (P.ref64)
-    ((double*)P.pref)[idx] += double(p);
-  else
-    ((float*)P.pref)[idx] += float(p);
-  // the step's explicit force from the re-based populations, as k_force
-  // (first-moment gradient only: it reads no neighbour's populations)
-  if (FORCE) {
-    double v3[3][3], gx, gy, px, py;
-    force_gather(sst, v3);
-    grad_c(v3, gx, gy);
-    force_moments(P, V, c, jx, jy, px, py);
-    force_write<T>(P, V, c, gx, gy, px, py);
-  }
+  if (FORCE) force_finish<T>(P, V, c, n, central, sst, sp);
 }
 
 // displacement and stress of the current populations (eqs. displacement,
@@ -1276,18 +1280,15 @@ hipError_t launch_init(const CellL& a, int ntiles, hipStream_t s) {
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_rebase(const CellL& a, int ntiles, bool flow, hipStream_t s) {
+hipError_t launch_rebase(const CellL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (flow)
-    hipLaunchKernelGGL((k_rebase<T, true>), dim3(ntiles), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_rebase<T, false>), dim3(ntiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_rebase<T, false>), dim3(ntiles), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_rebase_force(const CellL& a, int ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rebase<T, true, true>), dim3(ntiles), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_rebase<T, true>), dim3(ntiles), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T, bool SHIFT>
@@ -2320,8 +2321,8 @@ template hipError_t launch_force<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_force<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_init<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_init<double>(const CellL&, int, hipStream_t);
-template hipError_t launch_rebase<float>(const CellL&, int, bool, hipStream_t);
-template hipError_t launch_rebase<double>(const CellL&, int, bool, hipStream_t);
+template hipError_t launch_rebase<float>(const CellL&, int, hipStream_t);
+template hipError_t launch_rebase<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_rebase_force<float>(const CellL&, int, hipStream_t);
 template hipError_t launch_rebase_force<double>(const CellL&, int, hipStream_t);
 template hipError_t launch_extract<float, false>(const CellL&, int, hipStream_t);
