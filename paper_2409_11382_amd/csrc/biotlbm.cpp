@@ -711,6 +711,10 @@ struct Engine {
   hipGraphExec_t ad_graph[17] = {};
   bool ad_valid = false;
   bool xcd_order = true;
+  // V-cycles run the coarse tails of every problem in one launch at the
+  // deepest point of the cycle when the tails start at several depths
+  bool merge_tails = true;
+  int tail_all_off = 0, tail_all_cnt = 0, tail_depths = 0;
   bool fuse = true;  // two-application sweeps in the fixed-cycle schedule
   bool quad = true;  // four-application sweeps on small coarse levels
   // launch-shape bounds (cells a depth covers in all); bp_tuning
@@ -809,6 +813,13 @@ bp_status engine_upload(Engine& E) {
       if (E.probs[i]->lo.tail_depth == d && d > 0) tiles.push_back(make_int2((int)i, 0));
     E.depth[d].tail_cnt = (int)tiles.size() - E.depth[d].tail_off;
   }
+  // every problem's tail, with the depth of its top level
+  E.tail_all_off = (int)tiles.size();
+  for (size_t i = 0; i < np; ++i)
+    if (E.probs[i]->lo.tail_depth > 0) tiles.push_back(make_int2((int)i, E.probs[i]->lo.tail_depth));
+  E.tail_all_cnt = (int)tiles.size() - E.tail_all_off;
+  E.tail_depths = 0;
+  for (int d = 1; d < E.maxL; ++d) E.tail_depths += E.depth[d].tail_cnt > 0 ? 1 : 0;
   E.fine_off = (int)tiles.size();
   for (size_t i = 0; i < np; ++i) {
     const Prob& P = *E.probs[i];
@@ -932,7 +943,23 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool partials_last, bool
   if (d >= E.maxL) return;
   if (cyc < 0) cyc = E.cycle;
   const int full = tail ? 0 : 2, restr = full + 1;
-  if (tail && E.depth[d].tail_cnt > 0) {
+  // the tails of a V-cycle from zero in one launch where the cycle turns
+  // (problems are independent, and a problem's levels between its last
+  // pre-smoothing and first post-smoothing launch are its tail's alone)
+  const bool merged = tail && from_zero && cyc == BP_CYCLE_V && E.merge_tails && E.tail_depths >= 2;
+  auto merged_tail = [&]() {
+    Op o;
+    o.kind = OP_TAIL;
+    o.tl.probs = E.d_probs;
+    o.tl.pids = (const int*)(E.d_tiles + E.tail_all_off);
+    o.tl.depth = -1;  // each entry's own
+    o.tl.K = E.K;
+    o.tl.shape = BP_CYCLE_V;
+    o.tl.from_zero = 1;
+    o.count = E.tail_all_cnt;
+    ops.push_back(o);
+  };
+  if (tail && !merged && E.depth[d].tail_cnt > 0) {
     Op o;
     o.kind = OP_TAIL;
     o.tl.probs = E.d_probs;
@@ -946,7 +973,10 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool partials_last, bool
   }
   bool here = false;
   for (int g = 0; g < 3; ++g) here = here || E.depth[d].cnt[full][g] > 0;
-  if (!here) return;
+  if (!here) {
+    if (merged) merged_tail();  // the deepest depth reached holds tails only
+    return;
+  }
   fuse = fuse && tail;
   bool deeper = false;
   for (int g = 0; g < 3; ++g) deeper = deeper || E.depth[d].cnt[restr][g] > 0;
@@ -966,6 +996,8 @@ void add_vcycle(Engine& E, std::vector<Op>& ops, int d, bool partials_last, bool
       if (cyc == BP_CYCLE_W) add_vcycle(E, ops, d + 1, false, tail, fuse, BP_CYCLE_W, false);
       if (cyc == BP_CYCLE_F) add_vcycle(E, ops, d + 1, false, tail, fuse, BP_CYCLE_V, false);
     }
+  } else if (merged) {
+    merged_tail();  // the cycle turns at this depth
   }
   add_smoothing(E, ops, d, full, nsm, sel, false, true, partials_last && d == 0, fuse);
 }
@@ -1199,6 +1231,7 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   E.cycle = E.fmg ? BP_CYCLE_V : cycle;
   if (const char* e = std::getenv("BIOT_NO_GRAPH")) E.use_graph = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_XCD_ORDER")) E.xcd_order = (std::atoi(e) == 0);
+  if (const char* e = std::getenv("BIOT_NO_MERGE_TAIL")) E.merge_tails = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_FUSE")) E.fuse = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_NO_QUAD")) E.quad = (std::atoi(e) == 0);
   if (const char* e = std::getenv("BIOT_QUAD_MAX_CELLS")) E.quad_max_cells = std::atoll(e);
@@ -1622,8 +1655,9 @@ double op_bytes(const Engine& E, const Op& o) {
       // the levels of the tail, each application's populations and rhs once
       double b = 0.0;
       for (const Prob* P : E.probs) {
-        if (P->lo.tail_depth != o.tl.depth || o.tl.depth == 0) continue;
-        for (int l = 1; l <= P->L - o.tl.depth; ++l) {
+        const int td = o.tl.depth < 0 ? P->lo.tail_depth : o.tl.depth;
+        if (td <= 0 || P->lo.tail_depth != td) continue;
+        for (int l = 1; l <= P->L - td; ++l) {
           const double n = (double)P->lo.lv[l].nx * P->lo.lv[l].ny, ls = P->lo.lv[l].dbl ? 8.0 : 4.0;
           const int apps = l == 1 ? P->d.csweeps : 2 * E.K + 1;
           b += n * apps * 24.0 * ls;

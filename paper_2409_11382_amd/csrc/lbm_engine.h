@@ -133,7 +133,7 @@ struct TailL {
   const ProbD* probs;
   const int* pids;
   const int* skip;  // as in SweepL
-  int depth;       // depth of the tail's top level
+  int depth;       // depth of the tail's top level (< 0: each entry's own, V-cycles from zero)
   int K;           // smoothing steps
   int shape;       // cycle shape of this visit of the top level: 0 V, 1 W, 2 F
   int from_zero;   // the top level's iterate starts at zero (else from its buffer A)

@@ -2109,8 +2109,10 @@ template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
   if (a.skip && *a.skip) return;  // uniform over the grid
   extern __shared__ char lds[];
-  const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
-  tail_run<T, double>(P, P.L - a.depth, a.K, lds);
+  // (problem, depth) entries: with a.depth < 0 each problem's tail starts at
+  // the entry's depth, else at the launch's
+  const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];
+  tail_run<T, double>(P, P.L - (a.depth < 0 ? a.pids[2 * blockIdx.x + 1] : a.depth), a.K, lds);
 }
 
 hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
