@@ -709,6 +709,7 @@ struct Engine {
   std::vector<Op> ad_ops[17];
   bool ad_loop = false;  // AD_HEAD runs every cycle of a step (whole-problem tail)
   hipGraphExec_t ad_graph[17] = {};
+  hipEvent_t ad_event = nullptr;  // after the copy of the stop flag (engines that may allocate)
   bool ad_valid = false;
   bool xcd_order = true;
   // V-cycles run the coarse tails of every problem in one launch at the
@@ -1245,6 +1246,10 @@ bp_status engine_init(Engine& E, char* area, size_t area_bytes, size_t probs_cap
   if (hipHostMalloc((void**)&E.host_pin, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(BP_ERR_DEVICE, "hipHostMalloc failed");
   E.own_pin = true;
+  if (hipEventCreateWithFlags(&E.ad_event, hipEventDisableTiming) != hipSuccess) {
+    E.ad_event = nullptr;
+    return fail(BP_ERR_DEVICE, "hipEventCreate failed");
+  }
   return BP_OK;
 }
 
@@ -1259,6 +1264,8 @@ void engine_release(Engine& E) {
   if (E.host_pin && E.own_pin) (void)hipHostFree(E.host_pin);
   E.host_pin = nullptr;
   E.own_pin = false;
+  if (E.ad_event) (void)hipEventDestroy(E.ad_event);
+  E.ad_event = nullptr;
 }
 
 // one time step of every problem of the engine with a fixed number of
@@ -1287,16 +1294,21 @@ bp_status fixed_step(Engine& E) {
 // the step's cycles checks.  A unit is one test and the rest of its cycle.
 // The host predicts the tests a step needs (as many as the last step's), and
 // enqueues the units before the last one whole, then only the last one's
-// test, and reads the flag once: on the predicted stop no launch of an
-// abandoned cycle is enqueued; a stop earlier than predicted leaves launches
-// that return at once; a later one takes the rest of the unit and more units.
+// test, a copy of the flag, and, gated on a normal stop, the step's flow step
+// and the next step's start and first cycle; then it reads the flag.  On the
+// predicted stop no launch of an abandoned cycle is enqueued and the device
+// runs on while the host reads; a stop earlier than predicted leaves launches
+// that return at once; a later one takes the rest of the unit and more units
+// (the gated launches returned at once).
 enum AdPiece {
-  AD_HEAD,   // re-base, force, the stop flag's reset and the first cycle
-  AD_TEST,   // re-base, the first finest-level launch (norms) and the test
-  AD_REST,   // the rest of the cycle that a test let through
-  AD_END,    // flow step and step counter
-  AD_FULL8,  // eight units
-  AD_B1,     // AD_B1 + n - 1: n - 1 units and a test (n = 1 .. kAdUnits)
+  AD_HEAD,    // re-base and force, the first cycle, then the stop flag's reset
+  AD_HEAD_G,  // the same, run only after a normal stop of the step before
+  AD_TEST,    // re-base, the first finest-level launch (norms) and the test
+  AD_REST,    // the rest of the cycle that a test let through
+  AD_END,     // flow step and step counter
+  AD_END_G,   // the same, run only after a normal stop
+  AD_FULL8,   // eight units
+  AD_B1,      // AD_B1 + n - 1: n - 1 units and a test (n = 1 .. kAdUnits)
 };
 constexpr int kAdUnits = 8;  // graph boundaries cost ~8 us each
 static_assert(AD_B1 + kAdUnits <= 17, "adaptive pieces");
@@ -1311,6 +1323,15 @@ void set_skip(std::vector<Op>& ops, size_t from, const int* flag) {
   }
 }
 
+void set_need(std::vector<Op>& ops, const int* flag) {
+  for (Op& o : ops) {
+    o.sw.need = flag;
+    o.cl.need = flag;
+    o.pl.need = flag;
+    o.tl.need = flag;
+  }
+}
+
 bp_status build_adaptive(Engine& E) {
   Prob& P = *E.probs[0];
   for (auto& g : E.ad_graph) {
@@ -1321,7 +1342,6 @@ bp_status build_adaptive(Engine& E) {
   for (auto& o : E.ad_ops) o.clear();
   std::vector<Op>& head = E.ad_ops[AD_HEAD];
   head.push_back(cell_op(E, E.shift ? OP_REBASE_FORCE : OP_FORCE));  // as in the fixed-cycle step
-  head.push_back(prob_op(E, OP_AD_RESET));
   // a problem whose finest level fits one workgroup runs each cycle (after
   // the stopping test) as one whole-problem tail launch; the cycle's result
   // ends in buffer A as the tile schedule's does
@@ -1344,6 +1364,7 @@ bp_status build_adaptive(Engine& E) {
   E.ad_loop = full;
   if (full) {
     // every cycle of the step, with its stopping test, in one launch
+    head.push_back(prob_op(E, OP_AD_RESET));
     Op o = full_tail(0, E.K);
     o.tl.loop = 1;
     o.tl.ne_max = P.ne_max;
@@ -1354,6 +1375,9 @@ bp_status build_adaptive(Engine& E) {
       add_vcycle(E, head, 0, false, true, E.fuse, -1, true, false, true);
     else
       add_vcycle(E, head, 0, false, true, E.fuse);
+    head.push_back(prob_op(E, OP_AD_RESET));  // last: a gated head reads the flag it resets
+    E.ad_ops[AD_HEAD_G] = head;
+    set_need(E.ad_ops[AD_HEAD_G], P.d.ad);
     // a later cycle with the fixed schedule's launches; its first finest-level
     // launch measures ||g - S(g)|| and ||g|| on its first application (the
     // cycle's starting iterate), and the stopping test follows it.  On a stop
@@ -1385,6 +1409,10 @@ bp_status build_adaptive(Engine& E) {
   }
   E.ad_ops[AD_END].push_back(flow_op(E));
   E.ad_ops[AD_END].push_back(prob_op(E, OP_ADVANCE));
+  if (!full) {
+    E.ad_ops[AD_END_G] = E.ad_ops[AD_END];
+    set_need(E.ad_ops[AD_END_G], P.d.ad);
+  }
   if (E.use_graph && E.stream)
     for (int k = 0; k < AD_B1 + kAdUnits; ++k)
       if (!E.ad_ops[k].empty()) BPCHK(capture_ops(E, E.ad_ops[k], &E.ad_graph[k]));
@@ -1400,21 +1428,41 @@ bp_status run_adaptive(Engine& E, int k) {
   return run_ops(E, E.ad_ops[k]);
 }
 
-// the stop flag, the cycle count and the last ratio (adjacent on the device)
-bp_status read_stop(Engine& E, const Prob& P) {
+// copy the stop flag, the cycle count and the last ratio (adjacent on the
+// device) to the host
+bp_status copy_stop(Engine& E, const Prob& P) {
   HIPCHK(hipMemcpyAsync(E.host_pin, P.d.ad, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, E.stream));
-  HIPCHK(hipStreamSynchronize(E.stream));
+  if (E.ad_event) HIPCHK(hipEventRecord(E.ad_event, E.stream));
   return BP_OK;
 }
 
-bp_status adaptive_step(Engine& E) {
+// wait for that copy only (work enqueued after it keeps the device busy)
+bp_status wait_stop(Engine& E) {
+  if (E.ad_event)
+    HIPCHK(hipEventSynchronize(E.ad_event));
+  else
+    HIPCHK(hipStreamSynchronize(E.stream));
+  return BP_OK;
+}
+
+// one adaptive step.  head_queued: the step's start and first cycle are
+// already enqueued (gated on the step before); next: enqueue the next step's
+// the same way (another step of the same bp_step call follows)
+bp_status adaptive_step(Engine& E, bool& head_queued, bool next) {
   Prob& P = *E.probs[0];
-  if (!E.ad_valid) BPCHK(build_adaptive(E));
-  BPCHK(run_adaptive(E, AD_HEAD));
+  if (!E.ad_valid) {
+    BPCHK(build_adaptive(E));
+    head_queued = false;
+  }
+  if (!head_queued) BPCHK(run_adaptive(E, AD_HEAD));
+  head_queued = false;
   int* st = (int*)E.host_pin;
   if (E.ad_loop) {  // the whole-problem tail ran every cycle and test
-    BPCHK(read_stop(E, P));
+    BPCHK(copy_stop(E, P));
+    BPCHK(wait_stop(E));
     if (st[0] == 0) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
+    if (st[0] == 2) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
+    BPCHK(run_adaptive(E, AD_END));
   } else {
     // a step takes at most N_E,max tests (the last one stops)
     const int cap = std::max(1, P.ne_max);
@@ -1424,14 +1472,18 @@ bp_status adaptive_step(Engine& E) {
       for (; want > kAdUnits; want -= kAdUnits, issued += kAdUnits) BPCHK(run_adaptive(E, AD_FULL8));
       BPCHK(run_adaptive(E, AD_B1 + want - 1));
       issued += want;
-      BPCHK(read_stop(E, P));
+      BPCHK(copy_stop(E, P));
+      BPCHK(run_adaptive(E, AD_END_G));
+      if (next) BPCHK(run_adaptive(E, AD_HEAD_G));
+      BPCHK(wait_stop(E));
       if (st[0] != 0) break;
       if (issued >= cap) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
       BPCHK(run_adaptive(E, AD_REST));  // the cycle that the last test let through
       want = std::min(4, cap - issued);
     }
+    if (st[0] == 2) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
+    head_queued = next;
   }
-  if (st[0] == 2) return fail(BP_ERR_DIVERGED, "non-finite residual norm");
   const int j = st[1];
   P.last_ne = j;
   P.last_ratio = E.host_pin[1];
@@ -1440,7 +1492,6 @@ bp_status adaptive_step(Engine& E) {
   if (!(P.last_ratio <= P.ne_tol)) P.ad_at_cap += 1;  // stopped by ne_max
   P.ad_max_ratio = std::max(P.ad_max_ratio, P.last_ratio);
   P.ad_sum_ratio += P.last_ratio;
-  BPCHK(run_adaptive(E, AD_END));
   P.step += 1;
   return BP_OK;
 }
@@ -2069,8 +2120,9 @@ bp_status bp_step(bp_solver* s, int32_t nsteps) {
   if (!s) return fail(BP_ERR_ARG, "null solver");
   if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
   if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
+  bool head_queued = false;  // adaptive: the next step's start already enqueued
   for (int k = 0; k < nsteps; ++k) {
-    bp_status st = s->P.ne_fixed > 0 ? fixed_step(s->E) : adaptive_step(s->E);
+    bp_status st = s->P.ne_fixed > 0 ? fixed_step(s->E) : adaptive_step(s->E, head_queued, k + 1 < nsteps);
     if (st != BP_OK) {
       s->P.status = st;
       return st;

@@ -91,6 +91,8 @@ struct SweepL {
   int partials;   // write norm partials (finest level): 1 of the last application's input,
                   // 2 (multi-application launches) of the first application's input
   const int* skip;  // when set and *skip != 0 the launch does nothing (adaptive cycles past their stop)
+  const int* need;  // when set the launch runs only if *need == 1 (the adaptive step before it
+                    // stopped normally: work enqueued ahead of the host's read of the test)
   int eref_in;    // shifted storage: the displacement reference is eref (0) or eref2 (1)
   int rebase_out; // re-base the output on its displacement and write the new
                   // reference to the other buffer (finest level, smoothing)
@@ -105,12 +107,14 @@ struct CellL {    // per-cell kernels over the finest level
   const ProbD* probs;
   const int2* tiles;  // (problem, cell block)
   const int* skip;    // as in SweepL
+  const int* need;    // as in SweepL
 };
 
 struct ProbL {    // one block per problem
   const ProbD* probs;
   const int* pids;
   const int* skip;  // as in SweepL
+  const int* need;  // as in SweepL
   int fused;      // finalize: partials of the two-application sweep
   int advance;    // finalize: also count the completed step (after the flow step)
   int decide;     // finalize: then the adaptive stopping test (tol, ne_max)
@@ -133,6 +137,7 @@ struct TailL {
   const ProbD* probs;
   const int* pids;
   const int* skip;  // as in SweepL
+  const int* need;  // as in SweepL
   int depth;       // depth of the tail's top level (< 0: each entry's own, V-cycles from zero)
   int K;           // smoothing steps
   int shape;       // cycle shape of this visit of the top level: 0 V, 1 W, 2 F

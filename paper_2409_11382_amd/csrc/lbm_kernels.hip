@@ -46,12 +46,18 @@ __device__ constexpr double w9(int i) { return i == 0 ? 4.0 / 9 : (i < 5 ? 1.0 /
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// launches of the adaptive schedule: skip when a stop flag is set, or (need)
+// run only when the step before stopped normally
+__device__ __forceinline__ bool gated_off(const int* skip, const int* need) {
+  return (skip && *skip) || (need && *need != 1);
+}
+
 // ======================================================================
 // elastic tile sweep
 // ======================================================================
 template <typename T, typename Tc, int MODE, bool SHIFT>
 __global__ __launch_bounds__(256) void k_tsweep(SweepL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   constexpr int TY = kTileY;     // output rows
   constexpr int RR = TY + 4;     // region rows (two halo rows each side)
   constexpr int CR = TY + 2;     // collision rows
@@ -347,7 +353,7 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s) {
 // reference arithmetic is FP32 only.
 template <typename T, typename Tc, bool FINE, bool SHIFT, int APPS, bool RES, bool ALT, bool R64>
 __global__ __launch_bounds__((kWave * sweepn_waves<T, SHIFT, APPS + RES, ALT>())) void k_tsweep2(SweepL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   constexpr int A = APPS + (RES ? 1 : 0);
   static_assert(!ALT || A != 4, "four applications without the restriction have one region");
   constexpr int NW = sweepn_waves<T, SHIFT, A, ALT>();
@@ -792,6 +798,7 @@ hipError_t launch_tsweep2(const SweepL& a, int ntiles, bool ref64, hipStream_t s
 // ======================================================================
 template <typename T, bool SHIFT>
 __global__ __launch_bounds__(256) void k_tflow(CellL a) {
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   constexpr int TY = kTileY;
   constexpr int RR = TY + 2;                 // one halo row each side
   constexpr int NK = (RR + 3) / 4;
@@ -1102,6 +1109,7 @@ __device__ __forceinline__ void force_finish(const ProbD& P, const LevelD& V, co
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_force(CellL a) {
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   __shared__ double sst[kFRY][kFRX];
   __shared__ double sp[kFRY][kFRX];
   const int2 te = a.tiles[blockIdx.x];
@@ -1184,7 +1192,7 @@ __global__ __launch_bounds__(256) void k_init(CellL a) {
 // may read any neighbour.
 template <typename T, bool FORCE>
 __global__ __launch_bounds__(256) void k_rebase(CellL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   __shared__ double sst[FORCE ? kFRY : 1][kFRX];
   __shared__ double sp[FORCE ? kFRY : 1][kFRX];
   const int2 te = a.tiles[blockIdx.x];
@@ -2036,7 +2044,7 @@ __device__ __forceinline__ void tail_measure(const ProbD& P, char* lds, T (&G)[1
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_full(TailL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   extern __shared__ char lds[];
   const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
   const int L = P.L;
@@ -2097,7 +2105,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_full(TailL a) {
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail_shaped(TailL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   extern __shared__ char lds[];
   const ProbD& P = a.probs[a.pids[2 * blockIdx.x]];  // (problem, 0) entries
   const int lt = P.L - a.depth;
@@ -2107,7 +2115,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail_shaped(TailL a) {
 
 template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   extern __shared__ char lds[];
   // (problem, depth) entries: with a.depth < 0 each problem's tail starts at
   // the entry's depth, else at the launch's
@@ -2152,7 +2160,7 @@ hipError_t launch_tail(const TailL& a, int nprobs, bool dbl, hipStream_t s) {
 // ======================================================================
 // fixed-order FP64 sum of the finest level's norm partials
 __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
-  if (a.skip && *a.skip) return;  // uniform over the grid
+  if (gated_off(a.skip, a.need)) return;  // uniform over the grid
   const ProbD& P = a.probs[a.pids[blockIdx.x]];
   __shared__ double sr[256], sg[256];
   double r = 0.0, g = 0.0;
@@ -2208,6 +2216,7 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
 }
 
 __global__ void k_advance(ProbL a) {
+  if (gated_off(a.skip, a.need)) return;
   if (threadIdx.x == 0) *a.probs[a.pids[blockIdx.x]].phase += 1;
 }
 
@@ -2222,6 +2231,7 @@ __global__ __launch_bounds__(256) void k_zero(uint4* dst, size_t n16) {
 }
 
 __global__ void k_ad_reset(ProbL a) {
+  if (gated_off(a.skip, a.need)) return;
   if (threadIdx.x == 0) {
     const ProbD& P = a.probs[a.pids[0]];
     P.ad[0] = 0;
