@@ -177,7 +177,10 @@ bp_status bp_create(const bp_problem *p, void *device_ws, size_t ws_bytes, void 
  * the test on the device and enqueues the cycles in batches: it reads the
  * stop flag once per batch (as many cycles as the previous step needed, then
  * four at a time), or once per step where all of a step's cycles run in one
- * whole-problem launch. */
+ * whole-problem launch.  Within one call the flow step and the next step's
+ * first cycle are enqueued before each read, gated on a normal stop, so the
+ * device does not wait for the host; the call returns with its last step's
+ * work enqueued. */
 bp_status bp_step(bp_solver *s, int32_t nsteps);
 
 /* Replace body force f and fluid source s of eqs. 1-4 (host arrays, NULL =
