@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -223,12 +224,13 @@ void make_layout(const bp_problem* p, Layout& lo) {
   lo.ntiles_fine = sweep_tiles(p->nx, p->ny);
   lo.tail_depth = tail_depth_of(lo);
   lo.off_part = take((size_t)lo.ntiles_fine * 2 * 8);
-  // partials of the multi-application sweeps: as many tiles as the pair or
-  // the quad geometry has, whichever the schedule uses on the finest level
+  // partials of the multi-application sweeps: as many tiles as the largest
+  // of the geometries a finest-level launch may take (two or four
+  // applications, with or without the restriction, either region)
   lo.ntiles_fine2 = 0;
-  for (int A = 2; A <= 4; A += 2)
+  for (int A = 2; A <= 5; ++A)
     for (int alt = 0; alt < 2; ++alt)
-      lo.ntiles_fine2 = std::max(lo.ntiles_fine2, sweepn_tiles(p->nx, p->ny, lo.fdbl, A, lo.shift, alt && A == 2));
+      lo.ntiles_fine2 = std::max(lo.ntiles_fine2, sweepn_tiles(p->nx, p->ny, lo.fdbl, A, lo.shift, alt && A != 4));
   lo.off_part2 = take((size_t)lo.ntiles_fine2 * 2 * 8);
   lo.off_scal = take(128);
   if (lo.lag)
@@ -385,6 +387,7 @@ struct Prob {
   int step = 0;
   int64_t total_cycles = 0;
   int last_ne = 0;
+  int test_tiles = 0;  // adaptive: tiles of the launch that carries the stopping test's partials
   double last_ratio = -1.0;
   // adaptive statistics: steps, steps stopped at ne_max above the tolerance,
   // largest and summed end-of-step ratios
@@ -851,6 +854,7 @@ bp_status engine_upload(Engine& E) {
     const Prob& P = *E.probs[i];
     const int A0 = quad_at(E, 0) ? 4 : 2;
     pd[i].ntiles_fine2 = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, A0, E.shift, alt_at(E, 0, A0));
+    pd[i].ntiles_test = P.test_tiles;
   }
   std::vector<int> pids(np);
   for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
@@ -1395,8 +1399,15 @@ bp_status build_adaptive(Engine& E) {
     fin.pl.decide = 1;
     fin.pl.tol = P.ne_tol;
     fin.pl.ne_max = P.ne_max;
-    fin.pl.fused = u[c0].apps > 1 ? 1 : 0;
+    fin.pl.fused = u[c0].apps > 1 ? 2 : 0;
     u.insert(u.begin() + (std::ptrdiff_t)i, fin);
+    if (u[c0].apps > 1) {
+      // the tiles whose partials the test sums: those of that launch
+      P.test_tiles = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, u[c0].apps, E.shift, u[c0].alt);
+      HIPCHK(hipMemcpyAsync((char*)E.d_probs + offsetof(ProbD, ntiles_test), &P.test_tiles, sizeof(int),
+                            hipMemcpyHostToDevice, E.stream));
+      HIPCHK(hipStreamSynchronize(E.stream));
+    }
     set_skip(u, 0, P.d.ad);
     E.ad_ops[AD_TEST].assign(u.begin(), u.begin() + (std::ptrdiff_t)i + 1);
     E.ad_ops[AD_REST].assign(u.begin() + (std::ptrdiff_t)i + 1, u.end());

@@ -65,7 +65,8 @@ struct ProbD {
   double omf_u, alpha, alpha_h, h, r, b_s, b_d, inv_c0h;
   int ntiles_fine;            // sweep tiles of the finest level
   int grad_central;           // explicit force: central difference of p instead of first moments
-  int ntiles_fine2;           // two-application sweep tiles of the finest level
+  int ntiles_fine2;           // tiles of the finest level's last post-smoothing launch (multi-application)
+  int ntiles_test;            // tiles of the finest level's first pre-smoothing launch (the adaptive test)
   uint32_t* ttab;             // coarse tail: per-cell gather tables of levels 1.. (8 words per cell)
   void* addt;                 // whole-problem tail: the finest level's wall terms, 8 planes
                               // in the population precision (or null)
@@ -115,7 +116,8 @@ struct ProbL {    // one block per problem
   const int* pids;
   const int* skip;  // as in SweepL
   const int* need;  // as in SweepL
-  int fused;      // finalize: partials of the two-application sweep
+  int fused;      // finalize: partials of a multi-application launch: 1 the last post-smoothing
+                  // one (ntiles_fine2 tiles), 2 the first pre-smoothing one (ntiles_test)
   int advance;    // finalize: also count the completed step (after the flow step)
   int decide;     // finalize: then the adaptive stopping test (tol, ne_max)
   double tol;

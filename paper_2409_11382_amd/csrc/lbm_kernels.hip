@@ -2164,7 +2164,7 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
   const ProbD& P = a.probs[a.pids[blockIdx.x]];
   __shared__ double sr[256], sg[256];
   double r = 0.0, g = 0.0;
-  const int n = a.fused ? P.ntiles_fine2 : P.ntiles_fine;
+  const int n = a.fused == 2 ? P.ntiles_test : (a.fused ? P.ntiles_fine2 : P.ntiles_fine);
   const double* part = a.fused ? P.partials2 : P.partials;
   for (int k = threadIdx.x; k < n; k += 256) {
     r += part[2 * k];

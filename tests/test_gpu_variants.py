@@ -281,3 +281,59 @@ def test_lone_solver_reports_divergence(lbm):
     assert ei.value.code == lbm.BP_ERR_DIVERGED
     assert s.stats()["diverged"] == 1
     s.close()
+
+
+# ---------------------------------------------------------------- schedules
+@pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
+def test_merged_coarse_tails_equal_the_tails_at_their_own_depths(lbm, prec, monkeypatch):
+    """A batch whose problems' coarse tails start at three depths runs them in
+    one launch where the V-cycle turns; with BIOT_NO_MERGE_TAIL=1 each depth
+    launches its own.  Independent problems, the same kernels: bitwise equal."""
+    probs = [P.loaded_strip(n=64, alpha=0.7, ne_fixed=3), P.loaded_strip(n=128, nu=0.4, ne_fixed=3),
+             P.loaded_strip(n=256, alpha=0.5, ne_fixed=3)]
+    out = []
+    for merge in (True, False):
+        if merge:
+            monkeypatch.delenv("BIOT_NO_MERGE_TAIL", raising=False)
+        else:
+            monkeypatch.setenv("BIOT_NO_MERGE_TAIL", "1")
+        _say("merged tails" if merge else "tails per depth", prec)
+        b = lbm.Batch(probs, prec)
+        b.step(4)
+        out.append([b.fields(i) for i in range(len(probs))])
+        b.close()
+    for A, B in zip(*out):
+        assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_adaptive_steps_in_one_call_equal_steps_one_at_a_time(lbm, prec, tol):
+    """Within one bp_step call the adaptive schedule enqueues the flow step and
+    the next step's first cycle before it reads the stopping test, gated on a
+    normal stop; steps taken one call at a time read first.  Same launches in
+    the same order on the device: bitwise equal fields and the same cycle
+    counts, including steps whose count differs from the one before."""
+    p = P.loaded_strip(n=64, alpha=1.0, ne_fixed=0, ne_tol=tol, ne_max=20)
+    a, b = lbm.Solver(p, prec), lbm.Solver(p, prec)
+    a.step(8)
+    ne = []
+    for _ in range(8):
+        b.step(1)
+        ne.append(b.stats()["last_ne"])
+    A, B = a.fields(), b.fields()
+    sa, sb = a.stats(), b.stats()
+    _say("pipelined", prec, tol, ne, sa["total_cycles"], sb["total_cycles"])
+    assert sa["total_cycles"] == sb["total_cycles"] and sa["last_ne"] == sb["last_ne"]
+    assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+    a.close()
+    b.close()
+    # the finest level of 64^2 runs four applications per launch, the first
+    # with the restriction: its test sums that launch's partials; the counts
+    # are the oracle's own decisions
+    if prec == "fp64":
+        o = Oracle(p, threads=oracle_threads(), history=8)
+        o.step(8)
+        ne_o, _ = o.get_history()
+        assert ne == list(ne_o), (ne, list(ne_o))
+        assert rel(A["eta"], o.fields()["eta"]) < STEP_TOL and rel(A["p"], o.fields()["p"]) < STEP_TOL
