@@ -4,6 +4,7 @@
 // the coupled step of Algorithm 5, HIP-graph capture) and the C ABI of
 // biotlbm.h.  A single solver is an engine of one problem.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1177,8 +1178,26 @@ hipError_t run_op(const Engine& E, const Op& o) {
   return hipSuccess;
 }
 
+// host-side trace ranges (roctx; rocprofv3 --marker-trace records them, and
+// without a tool attached they cost a call each)
+struct TraceRange {
+  explicit TraceRange(const char* m) { roctxRangePushA(m); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
+std::string op_name(const Op& o);
+
+// a launch's trace name: the kernel family and the multigrid depth it sweeps
+std::string op_trace_name(const Op& o) {
+  const int d = o.kind == OP_SWEEP ? o.sw.depth : (o.kind == OP_TAIL ? o.tl.depth : -1);
+  return d >= 0 ? op_name(o) + " depth " + std::to_string(d) : op_name(o);
+}
+
 bp_status run_ops(const Engine& E, const std::vector<Op>& ops) {
   for (const Op& o : ops) {
+    TraceRange r(op_trace_name(o).c_str());
     hipError_t e = run_op(E, o);
     if (e != hipSuccess) return fail(BP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   }
@@ -1275,6 +1294,7 @@ void engine_release(Engine& E) {
 // one time step of every problem of the engine with a fixed number of
 // V-cycles: a captured HIP graph when a stream is given, else direct launches
 bp_status fixed_step(Engine& E) {
+  TraceRange r("coupled step");
   if (!E.graph_valid) BPCHK(build_graph(E));
   if (E.graph) {
     HIPCHK(hipGraphLaunch(E.graph, E.stream));
@@ -1460,6 +1480,7 @@ bp_status wait_stop(Engine& E) {
 // already enqueued (gated on the step before); next: enqueue the next step's
 // the same way (another step of the same bp_step call follows)
 bp_status adaptive_step(Engine& E, bool& head_queued, bool next) {
+  TraceRange r("coupled step, adaptive cycles");
   Prob& P = *E.probs[0];
   if (!E.ad_valid) {
     BPCHK(build_adaptive(E));
@@ -1775,8 +1796,11 @@ std::string op_name(const Op& o) {
     case OP_REBASE_FORCE: return "rebase+force";
     case OP_FINALIZE: return "finalize";
     case OP_ADVANCE: return "advance";
-    default: return "other";
+    case OP_AD_RESET: return "adaptive reset";
+    case OP_INIT: return "initial conditions";
+    case OP_EXTRACT: return "extract";
   }
+  return "other";
 }
 
 // ---- the static workspace of bp_create_static: one array per device, held
@@ -1853,6 +1877,7 @@ bp_status profile_engine(Engine& E, int32_t steps, bp_kernel_stat* out, int32_t 
   for (int k = 0; k < steps && rc == BP_OK; ++k) {
     for (size_t i = 0; i < ops.size() && rc == BP_OK; ++i) {
       if (hipEventRecord(ev[i], E.stream) != hipSuccess) rc = fail(BP_ERR_DEVICE, "hipEventRecord failed");
+      TraceRange tr(op_trace_name(ops[i]).c_str());
       const hipError_t le = run_op(E, ops[i]);
       if (le != hipSuccess) rc = fail(BP_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(le));
     }
@@ -2128,6 +2153,7 @@ bp_status bp_destroy(bp_solver* s) {
 }
 
 bp_status bp_step(bp_solver* s, int32_t nsteps) {
+  TraceRange trace_range("bp_step");
   if (!s) return fail(BP_ERR_ARG, "null solver");
   if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
   if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
@@ -2381,6 +2407,7 @@ bp_status bp_set_tuning(bp_solver* s, const bp_tuning* t) {
 }
 
 bp_status bp_autotune(bp_solver* s, int32_t steps, bp_tuning* out) {
+  TraceRange trace_range("autotune");
   if (!s) return fail(BP_ERR_ARG, "null solver");
   if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
   if (s->E.ne <= 0) return fail(BP_ERR_ARG, "autotuning needs a fixed number of V-cycles");
@@ -2561,6 +2588,7 @@ bp_status bp_batch_create(const bp_problem* probs, int32_t n, void* device_ws, s
 // the end a member that diverged leaves the engine's launches (its state and
 // fields stay as they are, its fields report BP_ERR_DIVERGED)
 bp_status bp_batch_step(bp_batch* b, int32_t nsteps) {
+  TraceRange trace_range("batch steps");
   if (!b) return fail(BP_ERR_ARG, "null batch");
   if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
   for (int k = 0; k < nsteps; ++k) {
@@ -2728,6 +2756,7 @@ bp_status server_sync_members(bp_server* s) {
 }  // namespace
 
 bp_status bp_server_advance(bp_server* s, int32_t nsteps, int32_t* n_active, int32_t* n_queued) {
+  TraceRange trace_range("server steps");
   if (!s || nsteps < 0) return fail(BP_ERR_ARG, "bad server arguments");
   for (int k = 0; k < nsteps; ++k) {
     BPCHK(server_admit(s));

@@ -177,6 +177,7 @@ def test_library_host_code_under_address_and_undefined_sanitizers(tmp_path):
                            "-Xarch_host", "-fno-omit-frame-pointer",
                            "-c", os.path.join(CSRC, "biotlbm.cpp"), "-o", obj],
                           stderr=subprocess.DEVNULL)
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib, obj, kernels])
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib, obj, kernels,
+                           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     out = _run(LIB_SCRIPT, CLANG_ASAN, {"SAN_LIB": lib})
     assert "library ok" in out
