@@ -337,3 +337,24 @@ def test_adaptive_steps_in_one_call_equal_steps_one_at_a_time(lbm, prec, tol):
         ne_o, _ = o.get_history()
         assert ne == list(ne_o), (ne, list(ne_o))
         assert rel(A["eta"], o.fields()["eta"]) < STEP_TOL and rel(A["p"], o.fields()["p"]) < STEP_TOL
+
+
+def test_adaptive_test_on_four_application_launches_follows_oracle(lbm):
+    """A finest level swept four applications at a time, the first launch
+    with the restriction in its 64 x 32 region (above 128^2 cells): the
+    stopping test sums that launch's partials, and the counts are the
+    oracle's own decisions at 1e-10 on the fields."""
+    p = mixed_walls(200, 152, seed=7).replace(K=4, ne_fixed=0, ne_tol=1e-6, ne_max=20)
+    s = lbm.Solver(p, "fp64")
+    ne = []
+    for _ in range(4):
+        s.step(1)
+        ne.append(s.stats()["last_ne"])
+    o = Oracle(p, threads=oracle_threads(), history=4)
+    o.step(4)
+    ne_o, _ = o.get_history()
+    _say("four-application adaptive", ne, list(ne_o))
+    assert ne == list(ne_o)
+    A, B = s.fields(), o.fields()
+    assert rel(A["eta"], B["eta"]) < STEP_TOL and rel(A["p"], B["p"]) < STEP_TOL
+    s.close()
