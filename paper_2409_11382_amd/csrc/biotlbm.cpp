@@ -388,7 +388,6 @@ struct Prob {
   int step = 0;
   int64_t total_cycles = 0;
   int last_ne = 0;
-  int test_tiles = 0;  // adaptive: tiles of the launch that carries the stopping test's partials
   double last_ratio = -1.0;
   // adaptive statistics: steps, steps stopped at ne_max above the tolerance,
   // largest and summed end-of-step ratios
@@ -706,6 +705,7 @@ struct Engine {
   int cell_off = 0, cell_cnt = 0; // finest-level cell blocks
   int init_off = 0, init_cnt = 0; // cell blocks of the problems still to initialise
   std::vector<Op> step_ops;
+  std::vector<ProbD> pd_host;  // the descriptors last uploaded (tile counts are patched per schedule)
   hipGraphExec_t graph = nullptr;
   bool graph_valid = false, use_graph = true;
   // adaptive schedule (single-problem engines): its fixed pieces, each an op
@@ -855,8 +855,9 @@ bp_status engine_upload(Engine& E) {
     const Prob& P = *E.probs[i];
     const int A0 = quad_at(E, 0) ? 4 : 2;
     pd[i].ntiles_fine2 = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, A0, E.shift, alt_at(E, 0, A0));
-    pd[i].ntiles_test = P.test_tiles;
+    pd[i].ntiles_test = pd[i].ntiles_fine2;  // both set again by the schedules that use them
   }
+  E.pd_host = pd;
   std::vector<int> pids(np);
   for (size_t i = 0; i < np; ++i) pids[i] = (int)i;
   if (np) {
@@ -1222,6 +1223,24 @@ bp_status capture_ops(Engine& E, const std::vector<Op>& ops, hipGraphExec_t* out
   return BP_OK;
 }
 
+// set one per-problem tile count of the device descriptors (field at byte
+// offset `field`) to the tiles of a finest-level launch of `apps`
+// applications in the region `alt`, and upload the descriptors
+bp_status upload_tile_counts(Engine& E, size_t field, int apps, bool alt) {
+  if (E.pd_host.size() != E.probs.size()) return fail(BP_ERR_STATE, "descriptors not uploaded");
+  for (size_t i = 0; i < E.probs.size(); ++i) {
+    const Prob& P = *E.probs[i];
+    const int n = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, apps, E.shift, alt);
+    std::memcpy((char*)&E.pd_host[i] + field, &n, sizeof(int));
+  }
+  if (!E.pd_host.empty()) {
+    HIPCHK(hipMemcpyAsync(E.d_probs, E.pd_host.data(), E.pd_host.size() * sizeof(ProbD), hipMemcpyHostToDevice,
+                          E.stream));
+    HIPCHK(hipStreamSynchronize(E.stream));
+  }
+  return BP_OK;
+}
+
 bp_status build_graph(Engine& E) {
   if (E.graph) {
     (void)hipGraphExecDestroy(E.graph);
@@ -1229,6 +1248,11 @@ bp_status build_graph(Engine& E) {
   }
   E.graph_valid = false;
   build_step_ops(E, E.step_ops);
+  // the step's norms are the partials of the multi-application launch that
+  // carries them (the last post-smoothing launch at depth 0): its tiles
+  for (const Op& o : E.step_ops)
+    if (o.kind == OP_SWEEP && o.sw.depth == 0 && o.sw.partials == 1 && o.apps > 1)
+      BPCHK(upload_tile_counts(E, offsetof(ProbD, ntiles_fine2), o.apps, o.alt));
   if (E.use_graph && E.stream) BPCHK(capture_ops(E, E.step_ops, &E.graph));
   E.graph_valid = true;
   return BP_OK;
@@ -1421,13 +1445,8 @@ bp_status build_adaptive(Engine& E) {
     fin.pl.ne_max = P.ne_max;
     fin.pl.fused = u[c0].apps > 1 ? 2 : 0;
     u.insert(u.begin() + (std::ptrdiff_t)i, fin);
-    if (u[c0].apps > 1) {
-      // the tiles whose partials the test sums: those of that launch
-      P.test_tiles = sweepn_tiles(P.nx, P.ny, P.lo.fdbl, u[c0].apps, E.shift, u[c0].alt);
-      HIPCHK(hipMemcpyAsync((char*)E.d_probs + offsetof(ProbD, ntiles_test), &P.test_tiles, sizeof(int),
-                            hipMemcpyHostToDevice, E.stream));
-      HIPCHK(hipStreamSynchronize(E.stream));
-    }
+    // the tiles whose partials the test sums: those of that launch
+    if (u[c0].apps > 1) BPCHK(upload_tile_counts(E, offsetof(ProbD, ntiles_test), u[c0].apps, u[c0].alt));
     set_skip(u, 0, P.d.ad);
     E.ad_ops[AD_TEST].assign(u.begin(), u.begin() + (std::ptrdiff_t)i + 1);
     E.ad_ops[AD_REST].assign(u.begin() + (std::ptrdiff_t)i + 1, u.end());
