@@ -167,7 +167,8 @@ hipError_t launch_tsweep(const SweepL& a, int ntiles, hipStream_t s);
 // default region and, chosen per depth by the cells it covers in all, an
 // alternative (ALT):
 // - pairs, with or without the restriction, take 64-cell rows.  By default 8
-//   waves of 3 rows (FP64: 2): two blocks share a CU and hide each other's
+//   waves of 3 rows (FP32 without shifted storage: 4, whose LDS then still
+//   fits two blocks; FP64: 2): two blocks share a CU and hide each other's
 //   barrier waits, which is what bounds large grids.  ALT, for depths that
 //   fill the chip about once: tall regions of 32 rows (16 waves x 2) and 36
 //   rows (12 waves x 3), 24 output rows, one block per CU on a 512^2 level and
@@ -185,7 +186,8 @@ __host__ __device__ constexpr int sweepn_waves() {
 template <typename T, bool SHIFT, int A, bool ALT>
 __host__ __device__ constexpr int sweepn_rows() {
   return A >= 4 ? ((A == 5 && ALT) ? 2 : 1)
-                : (A == 3 ? 3 : ((ALT && !(sizeof(T) == 8 && SHIFT)) ? 2 : (sizeof(T) == 8 ? 2 : 3)));
+                : ((sizeof(T) == 4 && !SHIFT && !ALT) ? 4
+                                                      : (A == 3 ? 3 : ((ALT && !(sizeof(T) == 8 && SHIFT)) ? 2 : (sizeof(T) == 8 ? 2 : 3))));
 }
 template <int A, bool ALT>
 __host__ __device__ constexpr int sweepn_cols() { return (A <= 3 || ALT) ? kWave : 32; }
