@@ -266,7 +266,7 @@ void make_layout(const bp_problem* p, Layout& lo) {
 // two-application lists for every level, its tail entry, the finest level again for the flow step, and the
 // finest level's cell blocks (twice: per-cell kernels and initialisation)
 size_t tile_entries_for(const Layout& lo) {
-  size_t t = 1;
+  size_t t = 2;  // the tail entry, at its depth and in the list of every problem's tail
   for (int l = 1; l <= lo.L; ++l)
   {
     t += (size_t)sweep_tiles(lo.lv[l].nx, lo.lv[l].ny) * 4;
