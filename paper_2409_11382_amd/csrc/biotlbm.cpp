@@ -1623,9 +1623,19 @@ bp_status time_steps(Engine& E, int n, double* ms) {
   return rc;
 }
 
+// the median of three timings of n steps (a single timing of a few steps
+// varies by about the 2% a candidate must win by)
+bp_status time_steps_median(Engine& E, int n, double* ms) {
+  double t[3];
+  for (double& v : t) BPCHK(time_steps(E, n, &v));
+  std::sort(t, t + 3);
+  *ms = t[1];
+  return BP_OK;
+}
+
 // Coordinate descent over the four launch-shape bounds: each bound in turn
 // takes the candidate whose steps run fastest (by more than 2% over the best
-// so far), the others held.  Timing advances the problems, so the engine is
+// so far, medians of three timings), the others held.  Timing advances the problems, so the engine is
 // re-initialised at the end: only engines that have not stepped are tuned.
 bp_status autotune(Engine& E, int steps, bp_tuning* out) {
   if (E.ne <= 0) return fail(BP_ERR_ARG, "autotuning needs a fixed number of V-cycles");
@@ -1639,7 +1649,7 @@ bp_status autotune(Engine& E, int steps, bp_tuning* out) {
                                      {0, 64 * 64, 128 * 128, 256 * 256, 512 * 512}};
   BPCHK(engine_upload(E));
   double best = 0.0;
-  BPCHK(time_steps(E, steps, &best));
+  BPCHK(time_steps_median(E, steps, &best));
   for (int k = 0; k < 4; ++k) {
     const int64_t keep = *knob[k];
     int64_t bestv = keep;
@@ -1648,7 +1658,7 @@ bp_status autotune(Engine& E, int steps, bp_tuning* out) {
       *knob[k] = cand[k][c];
       BPCHK(engine_upload(E));
       double ms = 0.0;
-      BPCHK(time_steps(E, steps, &ms));
+      BPCHK(time_steps_median(E, steps, &ms));
       if (ms < 0.98 * best) {
         best = ms;
         bestv = cand[k][c];
