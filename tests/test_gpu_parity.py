@@ -439,17 +439,20 @@ def test_checkpoint_resume_is_bitwise(lbm):
 
 
 @pytest.mark.parametrize("ref64", ["0", "1"])
-def test_checkpoint_shifted_storage(lbm, monkeypatch, ref64):
-    """FP32 shifted storage, FP32 and FP64 references.  A restored state is
-    split into references and offsets in FP64, so the round trip keeps what
-    FP32 full populations would round away: on a state with a displacement
-    and pressure of 1e3 (equilibria of ~300) it returns g and f within 1e-6
-    (FP32 full populations would lose ~2e-5).  A run resumed from a checkpoint
+@pytest.mark.parametrize("nsteps", [5, 6])
+def test_checkpoint_shifted_storage(lbm, monkeypatch, ref64, nsteps):
+    """FP32 shifted storage, FP32 and FP64 references, a checkpoint after an
+    odd and an even number of steps (the pressure reference alternates
+    between two buffers by step parity).  A restored state is split into
+    references and offsets in FP64, so the round trip keeps what FP32 full
+    populations would round away: on a state with a displacement and
+    pressure of 1e3 (equilibria of ~300) it returns g and f within 1e-6 (FP32
+    full populations would lose ~2e-5).  A run resumed from a checkpoint
     follows the uninterrupted run to rounding."""
     monkeypatch.setenv("BIOT_REF64", ref64)
     p = P.loaded_strip(n=64, alpha=0.8, ne_fixed=3)
     a = lbm.Solver(p, "fp32_shifted")
-    a.step(6)
+    a.step(nsteps)
     st = a.get_state()
     a.step(4)
     b = lbm.Solver(p, "fp32_shifted")
@@ -467,7 +470,7 @@ def test_checkpoint_shifted_storage(lbm, monkeypatch, ref64):
     b.set_state(f, g, st["D1"], st["D2"], step=st["step"])
     rt = b.get_state()
     eg, ef = np.abs(rt["g"] - g).max(), np.abs(rt["f"] - f).max()
-    _say("checkpoint shifted ref64", ref64, d, "round trip", eg, ef)
+    _say("checkpoint shifted ref64", ref64, "steps", nsteps, d, "round trip", eg, ef)
     assert max(d) < 1e-6, d
     assert eg < 1e-6 and ef < 1e-6, (eg, ef)
     a.close()
