@@ -207,6 +207,66 @@ def test_dirichlet_walls_give_second_order_displacement_without_grid_scale_oscil
         assert math.log2(c0 / c1) > 3.5, res
 
 
+def _quadratic_problem(n, els, lam=0.7, mu=0.4, c=(0.3, -0.2, 0.1, -0.15, 0.25, 0.05)):
+    """Elasticity alone (alpha = 0) with a quadratic displacement: linear
+    stress, so the traction along every traction wall varies linearly and the
+    body force -div sigma is constant (written out from the coefficients)."""
+    a1, a2, a3, b1, b2, b3 = c
+    h = 1.0 / n
+
+    def disp(x, y):
+        return a1 * x * x + a2 * x * y + a3 * y * y, b1 * x * x + b2 * x * y + b3 * y * y
+
+    def stress(x, y):
+        ux, uy = 2 * a1 * x + a2 * y, a2 * x + 2 * a3 * y
+        vx, vy = 2 * b1 * x + b2 * y, b2 * x + 2 * b3 * y
+        d = ux + vy
+        return lam * d + 2 * mu * ux, mu * (uy + vx), lam * d + 2 * mu * vy
+
+    # -div sigma with sigma11 = (lam + 2mu) ux + lam vy, sigma12 = mu (uy + vx),
+    # sigma22 = lam ux + (lam + 2mu) vy
+    f1 = -((lam + 2 * mu) * 2 * a1 + lam * b2 + mu * (2 * a3 + b2))
+    f2 = -(mu * (a2 + 2 * b1) + lam * a2 + (lam + 2 * mu) * 2 * b3)
+    idx = (np.arange(n) + 0.5) * h
+    geo = {P.LEFT: (np.zeros(n), idx, (-1, 0)), P.RIGHT: (np.ones(n), idx, (1, 0)),
+           P.BOTTOM: (idx, np.zeros(n), (0, -1)), P.TOP: (idx, np.ones(n), (0, 1))}
+    sides = []
+    for s, el in enumerate(els):
+        x, y, (nx_, ny_) = geo[s]
+        if el == P.EL_DIRICHLET:
+            val = np.stack(disp(x, y), 1)
+        else:
+            s11, s12, s22 = stress(x, y)
+            val = np.stack([s11 * nx_ + s12 * ny_, s12 * nx_ + s22 * ny_], 1)
+        sides.append(P.Side(el=el, flow=np.full(n, P.FLOW_NOFLOW, np.int8), el_value=val, p_value=np.zeros(n)))
+    p = P.Problem(nx=n, ny=n, dx=h, dt=h * h, lam=lam, mu=mu, c0=1.0, alpha=0.0, kappa=0.1, sides=sides,
+                  K=4, ne_fixed=120)
+    X, Y = p.cell_centres()
+    body = np.stack([np.full_like(X, f1), np.full_like(X, f2)])
+    return (p.replace(body_f=body, source_s=np.zeros((n, n))), np.stack(disp(X, Y)), np.stack(stress(X, Y)))
+
+
+@pytest.mark.parametrize("els", [(P.EL_DIRICHLET, P.EL_TRACTION, P.EL_TRACTION, P.EL_TRACTION),
+                                 (P.EL_TRACTION, P.EL_TRACTION, P.EL_DIRICHLET, P.EL_TRACTION)])
+def test_linearly_varying_traction_gives_second_order_displacement(els):
+    """The traction rule's link data (the traction at each link's wall
+    midpoint, from data given at face centres) on walls whose traction
+    varies linearly: the displacement converges at second order in the
+    maximum norm and the stress at first order, as Sec. 3.6 states for the
+    boundary schemes; data taken at the wrong point along a wall would leave
+    a first-order displacement error."""
+    res = []
+    for n in (8, 16, 32):
+        p, eta, sig = _quadratic_problem(n, els)
+        o = Oracle(p, threads=oracle_threads())
+        o.step(1)
+        F = o.fields()
+        res.append((np.abs(F["eta"] - eta).max(), np.abs(F["sigma"] - sig).max()))
+    (e0, s0), (e1, s1), (e2, s2) = res
+    assert math.log2(e0 / e1) > 1.9 and math.log2(e1 / e2) > 1.9, res
+    assert math.log2(s0 / s1) > 0.6 and math.log2(s1 / s2) > 0.9, res
+
+
 def _half_strip(full, n):
     sl = slice(n // 2, None)
     sides = list(full.sides)
