@@ -375,7 +375,8 @@ def cycle_shapes(n=512, steps=20):
     shifted storage, adaptive to ||g - S(g)|| <= 1e-6 ||g|| (at most 30
     cycles): milliseconds per step and mean cycles per step, after two untimed
     steps; the timed region ends with a device synchronisation (no field
-    copies)."""
+    copies).  The V-cycle is also compared with the fixed schedule running as
+    many cycles per step on average."""
     import torch
     from paper_2409_11382_amd import lbm
     from paper_2409_11382_amd import problem as P
@@ -394,6 +395,25 @@ def cycle_shapes(n=512, steps=20):
         s.close()
         out[name] = {"ms_per_step": round(1e3 * wall / steps, 3), "mean_cycles": round(cycles / steps, 2),
                      "ms_per_cycle": round(1e3 * wall / cycles, 3)}
+    # the fixed schedule at the V-cycle's mean count: a step of c fixed cycles
+    # costs base + c * per_cycle (every cycle the same launches), fitted from
+    # steps of two and three cycles
+    fixed = {}
+    for ne in (2, 3):
+        s = lbm.Solver(P.loaded_strip(n=n, alpha=1.0, ne_fixed=ne), "fp32_shifted")
+        s.step(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        fixed[ne] = 1e3 * (time.perf_counter() - t0) / steps
+        s.close()
+    per_cycle = fixed[3] - fixed[2]
+    same = fixed[2] + (out["V"]["mean_cycles"] - 2) * per_cycle
+    out["V_vs_fixed_same_cycles"] = {"fixed_ms_per_step": {"2": round(fixed[2], 4), "3": round(fixed[3], 4)},
+                                     "fixed_ms_per_added_cycle": round(per_cycle, 4),
+                                     "fixed_ms_per_step_at_V_mean_cycles": round(same, 4),
+                                     "ratio": round(out["V"]["ms_per_step"] / same, 3)}
     return out
 
 

@@ -388,6 +388,7 @@ struct Prob {
   int step = 0;
   int64_t total_cycles = 0;
   int last_ne = 0;
+  int prev_ne = 0;  // the count of the step before the last (adaptive prediction)
   double last_ratio = -1.0;
   // adaptive statistics: steps, steps stopped at ne_max above the tolerance,
   // largest and summed end-of-step ratios
@@ -1340,10 +1341,13 @@ bp_status fixed_step(Engine& E) {
 // once the ratio reaches the tolerance or j reaches N_E,max.  The test runs on
 // the device (in k_finalize) and sets a stop flag that every later launch of
 // the step's cycles checks.  A unit is one test and the rest of its cycle.
-// The host predicts the tests a step needs (as many as the last step's), and
+// The host predicts the tests a step needs (the fewer of the last two steps'
+// counts: a count that alternates between two values near the tolerance is
+// then predicted right every other step instead of never), and
 // enqueues the units before the last one whole, then only the last one's
 // test, a copy of the flag, and, gated on a normal stop, the step's flow step
-// and the next step's start and first cycle; then it reads the flag.  On the
+// and the next step's start and first cycle (one graph); then it reads the
+// flag.  On the
 // predicted stop no launch of an abandoned cycle is enqueued and the device
 // runs on while the host reads; a stop earlier than predicted leaves launches
 // that return at once; a later one takes the rest of the unit and more units
@@ -1359,7 +1363,8 @@ enum AdPiece {
   AD_B1,      // AD_B1 + n - 1: n - 1 units and a test (n = 1 .. kAdUnits)
 };
 constexpr int kAdUnits = 8;  // graph boundaries cost ~8 us each
-static_assert(AD_B1 + kAdUnits <= 17, "adaptive pieces");
+constexpr int AD_END_HEAD_G = AD_B1 + kAdUnits;  // AD_END_G then AD_HEAD_G in one graph
+static_assert(AD_END_HEAD_G + 1 <= 17, "adaptive pieces");
 
 void set_skip(std::vector<Op>& ops, size_t from, const int* flag) {
   for (size_t k = from; k < ops.size(); ++k) {
@@ -1462,9 +1467,12 @@ bp_status build_adaptive(Engine& E) {
   if (!full) {
     E.ad_ops[AD_END_G] = E.ad_ops[AD_END];
     set_need(E.ad_ops[AD_END_G], P.d.ad);
+    E.ad_ops[AD_END_HEAD_G] = E.ad_ops[AD_END_G];
+    E.ad_ops[AD_END_HEAD_G].insert(E.ad_ops[AD_END_HEAD_G].end(), E.ad_ops[AD_HEAD_G].begin(),
+                                   E.ad_ops[AD_HEAD_G].end());
   }
   if (E.use_graph && E.stream)
-    for (int k = 0; k < AD_B1 + kAdUnits; ++k)
+    for (int k = 0; k <= AD_END_HEAD_G; ++k)
       if (!E.ad_ops[k].empty()) BPCHK(capture_ops(E, E.ad_ops[k], &E.ad_graph[k]));
   E.ad_valid = true;
   return BP_OK;
@@ -1517,15 +1525,16 @@ bp_status adaptive_step(Engine& E, bool& head_queued, bool next) {
   } else {
     // a step takes at most N_E,max tests (the last one stops)
     const int cap = std::max(1, P.ne_max);
-    int want = std::min(cap, P.last_ne > 0 ? P.last_ne : 8);
+    int want = P.last_ne > 0 ? P.last_ne : 8;
+    if (P.prev_ne > 0) want = std::min(want, P.prev_ne);
+    want = std::min(cap, want);
     int issued = 0;
     for (;;) {
       for (; want > kAdUnits; want -= kAdUnits, issued += kAdUnits) BPCHK(run_adaptive(E, AD_FULL8));
       BPCHK(run_adaptive(E, AD_B1 + want - 1));
       issued += want;
       BPCHK(copy_stop(E, P));
-      BPCHK(run_adaptive(E, AD_END_G));
-      if (next) BPCHK(run_adaptive(E, AD_HEAD_G));
+      BPCHK(run_adaptive(E, next ? AD_END_HEAD_G : AD_END_G));
       BPCHK(wait_stop(E));
       if (st[0] != 0) break;
       if (issued >= cap) return fail(BP_ERR_STATE, "adaptive cycles did not stop");
@@ -1536,6 +1545,7 @@ bp_status adaptive_step(Engine& E, bool& head_queued, bool next) {
     head_queued = next;
   }
   const int j = st[1];
+  P.prev_ne = P.last_ne;
   P.last_ne = j;
   P.last_ratio = E.host_pin[1];
   P.total_cycles += j;
@@ -1671,6 +1681,7 @@ bp_status autotune(Engine& E, int steps, bp_tuning* out) {
   for (auto* P : E.probs) {
     P->total_cycles = 0;
     P->last_ne = 0;
+    P->prev_ne = 0;
   }
   if (out) {
     tuning_of(E, out);
