@@ -172,11 +172,11 @@ bp_status bp_create(const bp_problem *p, void *device_ws, size_t ws_bytes, void 
                     bp_solver **out);
 
 /* Advance nsteps coupled time steps (Algorithm 5).  Asynchronous on the
- * solver's stream in fixed-N_E mode (one captured HIP graph per step).  The
- * adaptive mode (Sec. 3.4 leaves the pseudo-time stopping test open) runs
- * the test on the device and enqueues the cycles in batches: it reads the
- * stop flag once per batch (as many cycles as the previous step needed, then
- * four at a time), or once per step where all of a step's cycles run in one
+ * solver's stream in fixed-N_E mode (captured HIP graphs of four steps, and
+ * of one for the rest).  The adaptive mode (Sec. 3.4 leaves the pseudo-time
+ * stopping test open) runs the test on the device and enqueues the cycles in
+ * batches: it reads the stop flag once per batch (as many cycles as the
+ * fewer of the last two steps needed, then four at a time), or once per step where all of a step's cycles run in one
  * whole-problem launch.  Within one call the flow step and the next step's
  * first cycle are enqueued before each read, gated on a normal stop, so the
  * device does not wait for the host; the call returns with its last step's

@@ -708,6 +708,7 @@ struct Engine {
   std::vector<Op> step_ops;
   std::vector<ProbD> pd_host;  // the descriptors last uploaded (tile counts are patched per schedule)
   hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph4 = nullptr;  // four steps in one graph (one graph boundary instead of four)
   bool graph_valid = false, use_graph = true;
   // adaptive schedule (single-problem engines): its fixed pieces, each an op
   // list and, with a stream, a captured graph (enum AdPiece below)
@@ -1247,6 +1248,10 @@ bp_status build_graph(Engine& E) {
     (void)hipGraphExecDestroy(E.graph);
     E.graph = nullptr;
   }
+  if (E.graph4) {
+    (void)hipGraphExecDestroy(E.graph4);
+    E.graph4 = nullptr;
+  }
   E.graph_valid = false;
   build_step_ops(E, E.step_ops);
   // the step's norms are the partials of the multi-application launch that
@@ -1254,7 +1259,12 @@ bp_status build_graph(Engine& E) {
   for (const Op& o : E.step_ops)
     if (o.kind == OP_SWEEP && o.sw.depth == 0 && o.sw.partials == 1 && o.apps > 1)
       BPCHK(upload_tile_counts(E, offsetof(ProbD, ntiles_fine2), o.apps, o.alt));
-  if (E.use_graph && E.stream) BPCHK(capture_ops(E, E.step_ops, &E.graph));
+  if (E.use_graph && E.stream) {
+    BPCHK(capture_ops(E, E.step_ops, &E.graph));
+    std::vector<Op> four;
+    for (int k = 0; k < 4; ++k) four.insert(four.end(), E.step_ops.begin(), E.step_ops.end());
+    BPCHK(capture_ops(E, four, &E.graph4));
+  }
   E.graph_valid = true;
   return BP_OK;
 }
@@ -1305,6 +1315,8 @@ void engine_release(Engine& E) {
   (void)hipStreamSynchronize(E.stream);  // queued work may still read the pinned staging buffer
   if (E.graph) (void)hipGraphExecDestroy(E.graph);
   E.graph = nullptr;
+  if (E.graph4) (void)hipGraphExecDestroy(E.graph4);
+  E.graph4 = nullptr;
   for (auto& g : E.ad_graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
@@ -1318,18 +1330,25 @@ void engine_release(Engine& E) {
 
 // one time step of every problem of the engine with a fixed number of
 // V-cycles: a captured HIP graph when a stream is given, else direct launches
-bp_status fixed_step(Engine& E) {
+// one fixed-cycle step, or four in one graph when `left` (the steps still to
+// take) allows; `left` is counted down by the steps enqueued
+bp_status fixed_step(Engine& E, int* left = nullptr) {
   TraceRange r("coupled step");
   if (!E.graph_valid) BPCHK(build_graph(E));
-  if (E.graph) {
+  int n = 1;
+  if (left && *left >= 4 && E.graph4) {
+    HIPCHK(hipGraphLaunch(E.graph4, E.stream));
+    n = 4;
+  } else if (E.graph) {
     HIPCHK(hipGraphLaunch(E.graph, E.stream));
   } else {
     BPCHK(run_ops(E, E.step_ops));
   }
+  if (left) *left -= n;
   for (auto* P : E.probs) {
-    P->step += 1;
+    P->step += n;
     P->last_ne = E.ne;
-    P->total_cycles += E.ne;
+    P->total_cycles += (int64_t)n * E.ne;
   }
   return BP_OK;
 }
@@ -1347,9 +1366,8 @@ bp_status fixed_step(Engine& E) {
 // enqueues the units before the last one whole, then only the last one's
 // test, a copy of the flag, and, gated on a normal stop, the step's flow step
 // and the next step's start and first cycle (one graph); then it reads the
-// flag.  On the
-// predicted stop no launch of an abandoned cycle is enqueued and the device
-// runs on while the host reads; a stop earlier than predicted leaves launches
+// flag.  On the predicted stop no launch of an abandoned cycle is enqueued and
+// the device runs on while the host reads; a stop earlier than predicted leaves launches
 // that return at once; a later one takes the rest of the unit and more units
 // (the gated launches returned at once).
 enum AdPiece {
@@ -2198,8 +2216,19 @@ bp_status bp_step(bp_solver* s, int32_t nsteps) {
   if (s->P.status != BP_OK) return fail(BP_ERR_STATE, "solver is in an error state");
   if (nsteps < 0) return fail(BP_ERR_ARG, "nsteps < 0");
   bool head_queued = false;  // adaptive: the next step's start already enqueued
+  if (s->P.ne_fixed > 0) {
+    int left = nsteps;
+    while (left > 0) {
+      bp_status st = fixed_step(s->E, &left);
+      if (st != BP_OK) {
+        s->P.status = st;
+        return st;
+      }
+    }
+    return BP_OK;
+  }
   for (int k = 0; k < nsteps; ++k) {
-    bp_status st = s->P.ne_fixed > 0 ? fixed_step(s->E) : adaptive_step(s->E, head_queued, k + 1 < nsteps);
+    bp_status st = adaptive_step(s->E, head_queued, k + 1 < nsteps);
     if (st != BP_OK) {
       s->P.status = st;
       return st;
