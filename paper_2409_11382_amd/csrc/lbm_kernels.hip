@@ -2165,10 +2165,22 @@ __global__ __launch_bounds__(256) void k_finalize(ProbL a) {
   __shared__ double sr[256], sg[256];
   double r = 0.0, g = 0.0;
   const int n = a.fused == 2 ? P.ntiles_test : (a.fused ? P.ntiles_fine2 : P.ntiles_fine);
-  const double* part = a.fused ? P.partials2 : P.partials;
-  for (int k = threadIdx.x; k < n; k += 256) {
-    r += part[2 * k];
-    g += part[2 * k + 1];
+  const double2* part = (const double2*)(a.fused ? P.partials2 : P.partials);
+  // each thread sums the pairs k = t, t + 256, ... in that order; eight loads
+  // are in flight at a time (an absent pair adds +0, which leaves the sums of
+  // squares unchanged)
+  for (int k0 = threadIdx.x; k0 < n; k0 += 8 * 256) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + 256 * u;
+      v[u] = k < n ? part[k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      r += v[u].x;
+      g += v[u].y;
+    }
   }
   sr[threadIdx.x] = r;
   sg[threadIdx.x] = g;
