@@ -307,6 +307,27 @@ def test_merged_coarse_tails_equal_the_tails_at_their_own_depths(lbm, prec, monk
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
+def test_fixed_steps_in_one_call_equal_steps_one_at_a_time(lbm, prec):
+    """A call of at least four fixed-cycle steps replays a graph of four
+    steps (then single steps for the rest); steps taken one call at a time
+    replay the one-step graph.  The same launches in the same order: bitwise
+    equal fields, step numbers and cycle counts after 4 + 4 + 3 steps."""
+    p = P.loaded_strip(n=128, alpha=1.0, ne_fixed=3, K=4)
+    a, b = lbm.Solver(p, prec), lbm.Solver(p, prec)
+    a.step(11)
+    for _ in range(11):
+        b.step(1)
+    A, B = a.fields(), b.fields()
+    sa, sb = a.stats(), b.stats()
+    _say("four-step graph", prec, sa["step"], sa["total_cycles"], sb["step"], sb["total_cycles"])
+    assert sa["step"] == sb["step"] == 11 and sa["total_cycles"] == sb["total_cycles"] == 33
+    assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+    assert np.array_equal(A["sigma"], B["sigma"])
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_shifted"])
 @pytest.mark.parametrize("tol", [1e-6, 1e-10])
 def test_adaptive_steps_in_one_call_equal_steps_one_at_a_time(lbm, prec, tol):
     """Within one bp_step call the adaptive schedule enqueues the flow step and
