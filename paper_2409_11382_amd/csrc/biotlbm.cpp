@@ -1328,10 +1328,10 @@ void engine_release(Engine& E) {
   E.ad_event = nullptr;
 }
 
-// one time step of every problem of the engine with a fixed number of
-// V-cycles: a captured HIP graph when a stream is given, else direct launches
-// one fixed-cycle step, or four in one graph when `left` (the steps still to
-// take) allows; `left` is counted down by the steps enqueued
+// time steps of every problem of the engine with a fixed number of V-cycles:
+// one step, or four in one graph when `left` (the steps still to take, counted
+// down by those enqueued) allows; captured HIP graphs when a stream is given,
+// else direct launches
 bp_status fixed_step(Engine& E, int* left = nullptr) {
   TraceRange r("coupled step");
   if (!E.graph_valid) BPCHK(build_graph(E));
@@ -1362,12 +1362,12 @@ bp_status fixed_step(Engine& E, int* left = nullptr) {
 // the step's cycles checks.  A unit is one test and the rest of its cycle.
 // The host predicts the tests a step needs (the fewer of the last two steps'
 // counts: a count that alternates between two values near the tolerance is
-// then predicted right every other step instead of never), and
-// enqueues the units before the last one whole, then only the last one's
-// test, a copy of the flag, and, gated on a normal stop, the step's flow step
-// and the next step's start and first cycle (one graph); then it reads the
-// flag.  On the predicted stop no launch of an abandoned cycle is enqueued and
-// the device runs on while the host reads; a stop earlier than predicted leaves launches
+// then predicted right every other step instead of never).  It enqueues the
+// units before the last one whole, then only the last one's test, a copy of
+// the flag, and, gated on a normal stop, the step's flow step and the next
+// step's start and first cycle (one graph); then it reads the flag.  On the
+// predicted stop no launch of an abandoned cycle is enqueued and the device
+// runs on while the host reads; a stop earlier than predicted leaves launches
 // that return at once; a later one takes the rest of the unit and more units
 // (the gated launches returned at once).
 enum AdPiece {
