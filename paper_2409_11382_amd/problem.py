@@ -254,7 +254,9 @@ def lognormal_permeability(n: int, sigma_log=1.0, corr=32.0, seed=0, ny=None) ->
     KX, KY = np.meshgrid(kx, ky)
     spec = np.exp(-(KX ** 2 + KY ** 2) * corr * corr / 8.0)  # sqrt of exp(-k^2 l^2/4)
     z = np.real(np.fft.ifft2(np.fft.fft2(w) * spec))
-    z = (z - z.mean()) / z.std()
+    sd = z.std()
+    # a grid too small for the correlation length can come out constant: kappa 1
+    z = (z - z.mean()) / sd if sd > 0 else np.zeros_like(z)
     return np.exp(sigma_log * z)
 
 

@@ -495,6 +495,46 @@ def test_full_size_loaded_strip_512(lbm):
         assert e[0] < tol and e[1] < tol
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 1), (4, 4, 2), (2, 8, 1), (8, 2, 1), (6, 6, 1)])
+def test_smallest_grids_match_oracle(lbm, shape):
+    """Grids of a few cells with every boundary type (one level, or two down
+    to 2 x 2): every cell is a wall cell and most tiles are mostly empty.
+    Three coupled steps against the oracle."""
+    nx, ny, levels = shape
+    p = mixed_walls(nx, ny, seed=9, levels=levels).replace(kappa=0.7, name=f"tiny_{nx}x{ny}")
+    o = Oracle(p, threads=1)
+    o.step(3)
+    B = o.fields()
+    for prec, tol in (("fp64", STEP_TOL), ("fp32_shifted", 1e-5)):
+        s = lbm.Solver(p, prec)
+        s.step(3)
+        A = s.fields()
+        s.close()
+        e = (rel(A["eta"], B["eta"]), rel(A["p"], B["p"]))
+        _say("tiny", shape, prec, e)
+        assert e[0] < tol and e[1] < tol, (shape, prec, e)
+
+
+def test_zero_steps_leave_the_initial_state(lbm):
+    """No step: the fields are the initial conditions (zero) at step 0; a
+    negative count is refused and leaves the solver usable; two steps after
+    that equal two steps of a fresh solver bitwise."""
+    p = P.loaded_strip(n=64, ne_fixed=2)
+    a, b = lbm.Solver(p, "fp32_shifted"), lbm.Solver(p, "fp32_shifted")
+    a.step(0)
+    F, st = a.fields(), a.stats()
+    assert st["step"] == 0 and st["total_cycles"] == 0
+    assert not np.any(F["eta"]) and not np.any(F["p"]) and not np.any(F["sigma"])
+    with pytest.raises(lbm.BiotError):
+        a.step(-1)
+    a.step(2)
+    b.step(2)
+    A, B = a.fields(), b.fields()
+    assert np.array_equal(A["eta"], B["eta"]) and np.array_equal(A["p"], B["p"])
+    a.close()
+    b.close()
+
+
 def test_invalid_problems_rejected(lbm):
     base = P.loaded_strip(n=16)
     for bad in (dict(c0=0.0), dict(alpha=1.5), dict(gamma=1.5), dict(levels=6)):
